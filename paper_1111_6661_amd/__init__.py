@@ -1,0 +1,227 @@
+"""MI355X cube statistics + histogram engine: Python binding of libcubestats.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libcubestats.so`` (see ``include/cubestats.h`` for the contract).
+The binding fails loudly when the library is missing or no GPU is present;
+there is no CPU fallback.
+
+Two layers:
+  * the C entry points under the same names (``cube_stats``, ``cube_hist``,
+    ``cube_stats_hist``, ``cube_stats_hist_minmax`` and the ``*_async``
+    forms), taking raw device addresses and integers;
+  * tensor helpers (``stats``, ``hist``, ``stats_hist``, ``stats_hist_minmax``)
+    that take a float32 torch tensor on the GPU -- 1-D, or 3-D indexed
+    [z, y, x] with unit x-stride -- and marshal its address and pitches.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcubestats.so")
+
+CUBE_OK, CUBE_EINVAL, CUBE_ENOMEM, CUBE_EDEVICE, CUBE_EBUSY = 0, -1, -2, -3, -4
+CUBE_MAX_BINS = 65536
+CUBE_NO_VALID, CUBE_HIST_BAD_RANGE = 1, 2
+CUBE_ACCUM_FP64MERGE, CUBE_ACCUM_KAHAN32, CUBE_ACCUM_NAIVE32 = 0, 1, 2
+
+
+class CubeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cubestats error {code}: {msg}")
+        self.code = code
+
+
+class cube_stats_t(C.Structure):
+    _fields_ = [("n_total", C.c_uint64), ("n_valid", C.c_uint64), ("n_nan", C.c_uint64),
+                ("min", C.c_float), ("max", C.c_float),
+                ("mean", C.c_double), ("m2", C.c_double), ("std", C.c_double),
+                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+assert C.sizeof(cube_stats_t) == 64
+
+
+@dataclass
+class Stats:
+    n_total: int
+    n_valid: int
+    n_nan: int
+    min: float
+    max: float
+    mean: float
+    m2: float
+    std: float
+    flags: int
+
+    @classmethod
+    def from_c(cls, s: cube_stats_t) -> "Stats":
+        return cls(s.n_total, s.n_valid, s.n_nan, s.min, s.max, s.mean, s.m2, s.std, s.flags)
+
+    @classmethod
+    def from_bytes(cls, b: bytes) -> "Stats":
+        return cls.from_c(cube_stats_t.from_buffer_copy(b))
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libcubestats.so (built in-tree by ``build.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_1111_6661_amd/build.py "
+                           "(or __graft_entry__.build()) first")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+    I64P = C.POINTER(C.c_int64)
+    lib.cube_abi_version.restype = C.c_int
+    lib.cube_last_error.restype = C.c_char_p
+    lib.cube_stats.argtypes = [P, i64, i64, i64, I64P, P]
+    lib.cube_hist.argtypes = [P, I64P, f32, f32, i32, P]
+    lib.cube_stats_hist.argtypes = [P, I64P, f32, f32, i32, P, P]
+    lib.cube_stats_hist_minmax.argtypes = [P, I64P, i32, P, P]
+    lib.cube_stats_async.argtypes = [P, I64P, P, P]
+    lib.cube_hist_async.argtypes = [P, I64P, f32, f32, i32, P, P]
+    lib.cube_stats_hist_async.argtypes = [P, I64P, f32, f32, i32, P, P, P]
+    lib.cube_stats_hist_minmax_async.argtypes = [P, I64P, i32, P, P, P]
+    lib.cube_set_accum_mode.argtypes = [i32]
+    lib.cube_set_launch.argtypes = [i32, i32, i32]
+    lib.cube_shutdown.restype = None
+    for name in ("cube_stats", "cube_hist", "cube_stats_hist", "cube_stats_hist_minmax",
+                 "cube_stats_async", "cube_hist_async", "cube_stats_hist_async",
+                 "cube_stats_hist_minmax_async", "cube_set_accum_mode", "cube_set_launch"):
+        getattr(lib, name).restype = C.c_int
+    if lib.cube_abi_version() != 1:
+        raise RuntimeError("libcubestats ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().cube_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise CubeError(rc, last_error())
+    return rc
+
+
+def _dims(dims) -> C.Array:
+    d = list(dims) + [0] * (5 - len(dims))
+    return (C.c_int64 * 5)(*d)
+
+
+# ------------------------------------------------------------ C entry points
+def cube_stats(ptr: int, nx: int, ny: int, nz: int, stride=None) -> Stats:
+    out = cube_stats_t()
+    st = (C.c_int64 * 2)(*stride) if stride is not None else None
+    _check(load().cube_stats(C.c_void_p(ptr), nx, ny, nz, st, C.byref(out)))
+    return Stats.from_c(out)
+
+
+def cube_hist(ptr: int, dims, lo: float, hi: float, nbins: int) -> np.ndarray:
+    counts = np.zeros(max(nbins, 0) + 3, dtype=np.uint64)
+    _check(load().cube_hist(C.c_void_p(ptr), _dims(dims), lo, hi, nbins, counts.ctypes.data))
+    return counts
+
+
+def cube_stats_hist(ptr: int, dims, lo: float, hi: float, nbins: int):
+    out = cube_stats_t()
+    counts = np.zeros(max(nbins, 0) + 3, dtype=np.uint64)
+    _check(load().cube_stats_hist(C.c_void_p(ptr), _dims(dims), lo, hi, nbins, C.byref(out),
+                                  counts.ctypes.data))
+    return Stats.from_c(out), counts
+
+
+def cube_stats_hist_minmax(ptr: int, dims, nbins: int):
+    out = cube_stats_t()
+    counts = np.zeros(max(nbins, 0) + 3, dtype=np.uint64)
+    _check(load().cube_stats_hist_minmax(C.c_void_p(ptr), _dims(dims), nbins, C.byref(out),
+                                         counts.ctypes.data))
+    return Stats.from_c(out), counts
+
+
+def cube_stats_async(ptr: int, dims, dev_out: int, stream: int = 0) -> None:
+    _check(load().cube_stats_async(C.c_void_p(ptr), _dims(dims), C.c_void_p(dev_out),
+                                   C.c_void_p(stream)))
+
+
+def cube_hist_async(ptr: int, dims, lo: float, hi: float, nbins: int, dev_counts: int,
+                    stream: int = 0) -> None:
+    _check(load().cube_hist_async(C.c_void_p(ptr), _dims(dims), lo, hi, nbins,
+                                  C.c_void_p(dev_counts), C.c_void_p(stream)))
+
+
+def cube_stats_hist_async(ptr: int, dims, lo: float, hi: float, nbins: int, dev_out: int,
+                          dev_counts: int, stream: int = 0) -> None:
+    _check(load().cube_stats_hist_async(C.c_void_p(ptr), _dims(dims), lo, hi, nbins,
+                                        C.c_void_p(dev_out), C.c_void_p(dev_counts),
+                                        C.c_void_p(stream)))
+
+
+def cube_stats_hist_minmax_async(ptr: int, dims, nbins: int, dev_out: int, dev_counts: int,
+                                 stream: int = 0) -> None:
+    _check(load().cube_stats_hist_minmax_async(C.c_void_p(ptr), _dims(dims), nbins,
+                                               C.c_void_p(dev_out), C.c_void_p(dev_counts),
+                                               C.c_void_p(stream)))
+
+
+def cube_set_accum_mode(mode: int) -> int:
+    return _check(load().cube_set_accum_mode(mode))
+
+
+def cube_set_launch(threads: int = 0, blocks: int = 0, hist_copies: int = 0) -> None:
+    _check(load().cube_set_launch(threads, blocks, hist_copies))
+
+
+def cube_shutdown() -> None:
+    load().cube_shutdown()
+
+
+# ------------------------------------------------------------ tensor helpers
+def box_of(t) -> tuple:
+    """(device address, [nx, ny, nz, sy, sz]) of a float32 CUDA tensor."""
+    import torch
+    if t.dtype != torch.float32:
+        raise TypeError("cube tensors are float32")
+    if not t.is_cuda:
+        raise ValueError("cube tensors live on the GPU")
+    if t.dim() == 1:
+        if t.numel() > 1 and t.stride(0) != 1:
+            raise ValueError("1-D cube tensors must be contiguous")
+        return t.data_ptr(), [t.numel(), 1, 1, t.numel(), t.numel()]
+    if t.dim() != 3:
+        raise ValueError("cube tensors are 1-D or 3-D [z, y, x]")
+    nz, ny, nx = t.shape
+    sz, sy, sx = t.stride()
+    if nx > 1 and sx != 1:
+        raise ValueError("the x axis must have unit stride")
+    return t.data_ptr(), [nx, ny, nz, sy if ny > 1 else nx, sz if nz > 1 else (sy if ny > 1 else nx) * ny]
+
+
+def stats(t) -> Stats:
+    ptr, d = box_of(t)
+    return cube_stats(ptr, d[0], d[1], d[2], (d[3], d[4]))
+
+
+def hist(t, lo: float, hi: float, nbins: int) -> np.ndarray:
+    ptr, d = box_of(t)
+    return cube_hist(ptr, d, lo, hi, nbins)
+
+
+def stats_hist(t, lo: float, hi: float, nbins: int):
+    ptr, d = box_of(t)
+    return cube_stats_hist(ptr, d, lo, hi, nbins)
+
+
+def stats_hist_minmax(t, nbins: int):
+    ptr, d = box_of(t)
+    return cube_stats_hist_minmax(ptr, d, nbins)

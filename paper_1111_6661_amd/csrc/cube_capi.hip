@@ -1,0 +1,572 @@
+// cube_capi.hip -- the C ABI of the cube statistics library: argument
+// validation, launch planning, per-stream workspaces and result copies.
+// Declarations and the contract of every entry point are in cubestats.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "cube_internal.h"
+
+using cube::Geom;
+using cube::HistRange;
+using cube::PassArgs;
+using cube::WaveRec;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(CUBE_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+std::atomic<int> g_accum{CUBE_ACCUM_FP64MERGE};
+std::atomic<int> g_threads{0}, g_blocks{0}, g_copies{0};
+
+constexpr int MAX_BLOCKS = 4096;
+constexpr int MAX_WAVES_PER_BLOCK = 16;
+constexpr size_t REC_CAP = (size_t)MAX_BLOCKS * MAX_WAVES_PER_BLOCK;
+constexpr size_t LDS_BUDGET = 80 * 1024;   // two histogram blocks per CU
+
+// One workspace per (device, stream): partial records, the ticket, the
+// histogram accumulators (kept at zero between launches by the kernel) and
+// the result staging buffers.
+struct Workspace {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    WaveRec *recs = nullptr;
+    unsigned int *ticket = nullptr;
+    unsigned long long *hist_acc = nullptr;
+    cube_stats_t *d_out = nullptr;
+    unsigned long long *d_counts = nullptr;
+    HistRange *d_range = nullptr;
+    cube_stats_t *h_out = nullptr;        // pinned
+    unsigned long long *h_counts = nullptr;
+    std::mutex mu;                        // held by synchronous calls
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+std::map<int, int> g_cus;
+
+void free_ws(Workspace *w)
+{
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(w->device);
+    hipStreamSynchronize(w->stream);
+    hipFree(w->recs);
+    hipFree(w->ticket);
+    hipFree(w->hist_acc);
+    hipFree(w->d_out);
+    hipFree(w->d_counts);
+    hipFree(w->d_range);
+    hipHostFree(w->h_out);
+    hipHostFree(w->h_counts);
+    hipSetDevice(prev);
+    delete w;
+}
+
+int get_ws(hipStream_t s, Workspace **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, s);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        *out = it->second;
+        return CUBE_OK;
+    }
+    Workspace *w = new Workspace;
+    w->device = dev;
+    w->stream = s;
+    const size_t nacc = (size_t)CUBE_MAX_BINS + 3;
+    bool ok = hipMalloc(&w->recs, REC_CAP * sizeof(WaveRec)) == hipSuccess &&
+              hipMalloc(&w->ticket, 256) == hipSuccess &&
+              hipMalloc(&w->hist_acc, nacc * 8) == hipSuccess &&
+              hipMalloc(&w->d_out, sizeof(cube_stats_t)) == hipSuccess &&
+              hipMalloc(&w->d_counts, nacc * 8) == hipSuccess &&
+              hipMalloc(&w->d_range, 256) == hipSuccess &&
+              hipHostMalloc(&w->h_out, sizeof(cube_stats_t)) == hipSuccess &&
+              hipHostMalloc(&w->h_counts, nacc * 8) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        free_ws(w);
+        return fail(CUBE_ENOMEM, "workspace allocation failed");
+    }
+    if ((e = hipMemset(w->ticket, 0, 256)) != hipSuccess ||
+        (e = hipMemset(w->hist_acc, 0, nacc * 8)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        free_ws(w);
+        return hip_fail(e, "workspace initialisation");
+    }
+    g_ws[key] = w;
+    *out = w;
+    return CUBE_OK;
+}
+
+int cu_count()
+{
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cus.find(dev);
+    if (it != g_cus.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n < 1)
+        n = 256;
+    g_cus[dev] = n;
+    return n;
+}
+
+// ---------------------------------------------------------------- validation
+struct Box {
+    const float *ptr;
+    int64_t nx, ny, nz, sy, sz;
+    uint64_t n;
+};
+
+int check_box(const float *ptr, const int64_t *dims, Box *b)
+{
+    if (!dims) return fail(CUBE_EINVAL, "dims is NULL");
+    b->ptr = ptr;
+    b->nx = dims[0];
+    b->ny = dims[1];
+    b->nz = dims[2];
+    if (b->nx < 0 || b->ny < 0 || b->nz < 0)
+        return fail(CUBE_EINVAL, "negative extent (%lld, %lld, %lld)", (long long)b->nx,
+                    (long long)b->ny, (long long)b->nz);
+    b->sy = dims[3] == 0 ? b->nx : dims[3];
+    b->sz = dims[4] == 0 ? b->sy * b->ny : dims[4];
+    if (b->nx == 0 || b->ny == 0 || b->nz == 0) {
+        b->n = 0;
+        return CUBE_OK;
+    }
+    if (b->nx > (int64_t)1 << 40 || b->ny > (int64_t)1 << 40 || b->nz > (int64_t)1 << 40)
+        return fail(CUBE_EINVAL, "extent too large");
+    if (b->ny > 1 && b->sy < b->nx)
+        return fail(CUBE_EINVAL, "row pitch sy=%lld < nx=%lld", (long long)b->sy,
+                    (long long)b->nx);
+    if (b->nz > 1 && b->sz < (b->ny > 1 ? b->sy * (b->ny - 1) : 0) + b->nx)
+        return fail(CUBE_EINVAL, "plane pitch sz=%lld overlaps the previous plane",
+                    (long long)b->sz);
+    if (b->ny > 1 && b->sy < 0) return fail(CUBE_EINVAL, "negative row pitch");
+    if (b->nz > 1 && b->sz < 0) return fail(CUBE_EINVAL, "negative plane pitch");
+    b->n = (uint64_t)b->nx * (uint64_t)b->ny * (uint64_t)b->nz;
+    if (!ptr) return fail(CUBE_EINVAL, "data pointer is NULL");
+    if ((uintptr_t)ptr & 3) return fail(CUBE_EINVAL, "data pointer is not 4-byte aligned");
+    return CUBE_OK;
+}
+
+// Checks that need the HIP runtime (after check_box succeeded).
+int check_box_device(const Box *b)
+{
+    const float *ptr = b->ptr;
+    if (b->n == 0) return CUBE_OK;
+    // The pointer must be device memory and the whole box must lie inside
+    // its allocation: a read outside it would fault the GPU.
+    hipPointerAttribute_t pa;
+    hipError_t e = hipPointerGetAttributes(&pa, ptr);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        return fail(CUBE_EINVAL, "data pointer is not GPU memory");
+    }
+    if (pa.type != hipMemoryTypeDevice && pa.type != hipMemoryTypeManaged)
+        return fail(CUBE_EINVAL, "data pointer is not device memory");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        return fail(CUBE_EINVAL, "cannot find the allocation of the data pointer");
+    }
+    const uint64_t last = (uint64_t)(b->nz - 1) * (uint64_t)(b->nz > 1 ? b->sz : 0) +
+                          (uint64_t)(b->ny - 1) * (uint64_t)(b->ny > 1 ? b->sy : 0) +
+                          (uint64_t)b->nx;  // one past the last voxel, in floats
+    const uintptr_t end = (uintptr_t)ptr + last * 4u;
+    if (end > (uintptr_t)base + size || end < (uintptr_t)ptr)
+        return fail(CUBE_EINVAL, "box extends past the end of its allocation");
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (pa.device != dev)
+        return fail(CUBE_EINVAL, "data lives on device %d, current device is %d", pa.device,
+                    dev);
+    return CUBE_OK;
+}
+
+int check_range(float lo, float hi, int32_t nbins, HistRange *r)
+{
+    if (nbins < 1 || nbins > CUBE_MAX_BINS)
+        return fail(CUBE_EINVAL, "nbins=%d outside [1, %d]", nbins, CUBE_MAX_BINS);
+    if (isnan(lo) || isnan(hi)) return fail(CUBE_EINVAL, "NaN histogram bound");
+    if (isinf(lo) || isinf(hi)) return fail(CUBE_EINVAL, "infinite histogram bound");
+    if (hi < lo) return fail(CUBE_EINVAL, "hi < lo");
+    volatile float width = hi - lo;  // one FP32 rounding, as the kernels see it
+    if (isinf(width)) return fail(CUBE_EINVAL, "hi - lo overflows float32");
+    float scale = 0.f;
+    if (width != 0.f) {
+        volatile float nb = (float)nbins;
+        scale = nb / width;
+        if (isinf(scale)) return fail(CUBE_EINVAL, "range too narrow for %d bins", nbins);
+    }
+    r->lo = lo;
+    r->hi = hi;
+    r->scale = scale;
+    r->ok = 1;
+    return CUBE_OK;
+}
+
+// ------------------------------------------------------------------ planning
+struct Plan {
+    Geom g;
+    int threads, blocks, copies_log2, hist;
+    size_t lds;
+};
+
+void collapse(const Box &b, Geom *g)
+{
+    int64_t row = b.nx, ny = 1, sy = 0, nz = 1, sz = 0;
+    const int64_t n[2] = {b.ny, b.nz}, st[2] = {b.sy, b.sz};
+    for (int k = 0; k < 2; ++k) {
+        if (n[k] == 1) continue;
+        if (ny == 1 && st[k] == row)
+            row *= n[k];
+        else if (ny == 1) {
+            ny = n[k];
+            sy = st[k];
+        } else if (st[k] == ny * sy)
+            ny *= n[k];
+        else {
+            nz = n[k];
+            sz = st[k];
+        }
+    }
+    g->ptr = b.ptr;
+    g->row_len = row;
+    g->ny = ny;
+    g->nz = nz;
+    g->sy = sy;
+    g->sz = sz;
+    g->n_total = b.n;
+}
+
+int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
+{
+    collapse(b, &p->g);
+    int threads = g_threads.load();
+    if (threads != 256 && threads != 512 && threads != 1024) threads = hist_kind_req ? 512 : 256;
+    p->threads = threads;
+    p->hist = cube::HIST_NONE;
+    p->copies_log2 = 0;
+    if (hist_kind_req) {
+        if (nbins > 32768) {
+            p->hist = cube::HIST_GLOBAL;
+        } else {
+            p->hist = cube::HIST_LDS;
+            int c = g_copies.load();
+            int clog = 0;
+            if (c > 0) {
+                while ((1 << (clog + 1)) <= c && clog < 5) ++clog;
+            } else {
+                const size_t words = LDS_BUDGET / 4;
+                while (clog < 5 && (size_t)(nbins + 2) << (clog + 1) <= words) ++clog;
+            }
+            while (clog > 0 && ((size_t)(nbins + 2) << clog) * 4 > 160 * 1024) --clog;
+            p->copies_log2 = clog;
+        }
+    }
+    p->lds = cube::pass_lds_bytes(stats, p->hist, nbins, p->copies_log2, threads);
+    const int bpc = cube::pass_blocks_per_cu(stats, p->hist, threads, p->lds);
+    const long long cap = (long long)cu_count() * bpc;
+    const long long per_block_min = (long long)threads * 16 * 2;  // two main-loop steps
+    long long blocks = g_blocks.load();
+    if (blocks <= 0) {
+        blocks = (long long)((b.n + per_block_min - 1) / per_block_min);
+        if (blocks > cap) blocks = cap;
+    }
+    // Per-block LDS counters are 32-bit: keep every block under 2^31 voxels.
+    const long long min_blocks = (long long)(b.n >> 31) + 1;
+    if (blocks < min_blocks) blocks = min_blocks;
+    if (blocks < 1) blocks = 1;
+    if (blocks > MAX_BLOCKS) blocks = MAX_BLOCKS;
+    if ((size_t)blocks * (threads / 64) > REC_CAP) blocks = (long long)(REC_CAP / (threads / 64));
+    p->blocks = (int)blocks;
+
+    Geom &g = p->g;
+    const long long rows = g.ny * g.nz;
+    long long segs = 1;
+    if (rows < blocks) segs = (blocks + rows - 1) / rows;
+    long long seg_len = (g.row_len + segs - 1) / segs;
+    seg_len = (seg_len + 3) & ~3LL;
+    if (seg_len < 4) seg_len = 4;
+    segs = (g.row_len + seg_len - 1) / seg_len;
+    g.seg_len = seg_len;
+    g.segs = segs;
+    g.n_units = rows * segs;
+    return CUBE_OK;
+}
+
+__global__ void k_write_empty(cube_stats_t *out, unsigned long long *counts, int nbins)
+{
+    const float qn = __int_as_float(0x7fc00000);
+    if (out && threadIdx.x == 0) {
+        cube_stats_t o;
+        o.n_total = o.n_valid = o.n_nan = 0;
+        o.min = o.max = qn;
+        o.mean = o.m2 = o.std = (double)qn;
+        o.flags = CUBE_NO_VALID;
+        o.reserved = 0;
+        *out = o;
+    }
+    if (counts)
+        for (int i = threadIdx.x; i < nbins + 3; i += blockDim.x) counts[i] = 0ull;
+}
+
+int launch(const PassArgs &a, const Plan &p, bool stats, hipStream_t s)
+{
+    hipError_t e = cube::launch_pass(a, stats, p.hist, p.threads, p.blocks, p.lds, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return CUBE_OK;
+}
+
+PassArgs base_args(const Workspace *w, const Plan &p, int nbins)
+{
+    PassArgs a;
+    memset(&a, 0, sizeof a);
+    a.g = p.g;
+    a.nbins = nbins;
+    a.copies_log2 = p.copies_log2;
+    a.recs = w->recs;
+    a.ticket = w->ticket;
+    a.hist_acc = w->hist_acc;
+    a.accum_mode = g_accum.load();
+    return a;
+}
+
+// The four operations, stream-ordered, with device outputs.
+enum Op { OP_STATS, OP_HIST, OP_FUSED, OP_MINMAX };
+
+int run_async(Op op, const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
+              cube_stats_t *dev_out, unsigned long long *dev_counts, hipStream_t s,
+              Workspace *w)
+{
+    Box b;
+    int rc = check_box(ptr, dims, &b);
+    if (rc) return rc;
+    if ((rc = check_box_device(&b))) return rc;
+    HistRange range = {0.f, 0.f, 0.f, 1};
+    if (op == OP_HIST || op == OP_FUSED) {
+        if ((rc = check_range(lo, hi, nbins, &range))) return rc;
+    } else if (op == OP_MINMAX) {
+        if (nbins < 1 || nbins > CUBE_MAX_BINS)
+            return fail(CUBE_EINVAL, "nbins=%d outside [1, %d]", nbins, CUBE_MAX_BINS);
+    }
+    if (op != OP_HIST && !dev_out) return fail(CUBE_EINVAL, "stats output is NULL");
+    if (op != OP_STATS && !dev_counts) return fail(CUBE_EINVAL, "counts output is NULL");
+    if (b.n == 0) {
+        hipLaunchKernelGGL(k_write_empty, dim3(1), dim3(256), 0, s,
+                           op == OP_HIST ? nullptr : dev_out,
+                           op == OP_STATS ? nullptr : dev_counts, nbins);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? CUBE_OK : hip_fail(e, "empty-box launch");
+    }
+    Plan p;
+    if (op == OP_STATS || op == OP_MINMAX) {
+        if ((rc = make_plan(b, true, 0, nbins, &p))) return rc;
+        PassArgs a = base_args(w, p, nbins);
+        a.out = dev_out;
+        if (op == OP_MINMAX) {
+            a.want_range = 1;
+            a.out_range = w->d_range;
+        }
+        if ((rc = launch(a, p, true, s))) return rc;
+        if (op == OP_STATS) return CUBE_OK;
+        Plan p2;
+        if ((rc = make_plan(b, false, 1, nbins, &p2))) return rc;
+        PassArgs a2 = base_args(w, p2, nbins);
+        a2.dev_range = w->d_range;
+        a2.counts = dev_counts;
+        return launch(a2, p2, false, s);
+    }
+    const bool stats = op == OP_FUSED;
+    if ((rc = make_plan(b, stats, 1, nbins, &p))) return rc;
+    PassArgs a = base_args(w, p, nbins);
+    a.range = range;
+    a.out = dev_out;
+    a.counts = dev_counts;
+    return launch(a, p, stats, s);
+}
+
+// Argument checks that need no GPU: done before any HIP call.
+int precheck(Op op, const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins)
+{
+    Box b;
+    int rc = check_box(ptr, dims, &b);
+    if (rc) return rc;
+    HistRange r;
+    if (op == OP_HIST || op == OP_FUSED) return check_range(lo, hi, nbins, &r);
+    if (op == OP_MINMAX && (nbins < 1 || nbins > CUBE_MAX_BINS))
+        return fail(CUBE_EINVAL, "nbins=%d outside [1, %d]", nbins, CUBE_MAX_BINS);
+    return CUBE_OK;
+}
+
+int run_sync(Op op, const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
+             cube_stats_t *out, uint64_t *counts)
+{
+    if (op != OP_HIST && !out) return fail(CUBE_EINVAL, "stats output is NULL");
+    if (op != OP_STATS && !counts) return fail(CUBE_EINVAL, "counts output is NULL");
+    int rc = precheck(op, ptr, dims, lo, hi, nbins);
+    if (rc) return rc;
+    Workspace *w = nullptr;
+    rc = get_ws(nullptr, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    rc = run_async(op, ptr, dims, lo, hi, nbins, w->d_out, w->d_counts, nullptr, w);
+    if (rc) return rc;
+    hipError_t e;
+    if (op != OP_HIST &&
+        (e = hipMemcpyAsync(w->h_out, w->d_out, sizeof(cube_stats_t), hipMemcpyDeviceToHost,
+                            nullptr)) != hipSuccess)
+        return hip_fail(e, "result copy");
+    if (op != OP_STATS &&
+        (e = hipMemcpyAsync(w->h_counts, w->d_counts, ((size_t)nbins + 3) * 8,
+                            hipMemcpyDeviceToHost, nullptr)) != hipSuccess)
+        return hip_fail(e, "counts copy");
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e, "synchronize");
+    if (op != OP_HIST) *out = *w->h_out;
+    if (op != OP_STATS) memcpy(counts, w->h_counts, ((size_t)nbins + 3) * 8);
+    if (op == OP_MINMAX && (w->h_out->flags & CUBE_HIST_BAD_RANGE))
+        return fail(CUBE_EINVAL, "the data range [min, max] is not a valid histogram range");
+    return CUBE_OK;
+}
+
+int run_async_entry(Op op, const float *ptr, const int64_t *dims, float lo, float hi,
+                    int32_t nbins, cube_stats_t *dev_out, uint64_t *dev_counts, void *stream)
+{
+    if (op != OP_HIST && !dev_out) return fail(CUBE_EINVAL, "stats output is NULL");
+    if (op != OP_STATS && !dev_counts) return fail(CUBE_EINVAL, "counts output is NULL");
+    int rc = precheck(op, ptr, dims, lo, hi, nbins);
+    if (rc) return rc;
+    Workspace *w = nullptr;
+    rc = get_ws((hipStream_t)stream, &w);
+    if (rc) return rc;
+    return run_async(op, ptr, dims, lo, hi, nbins, dev_out, (unsigned long long *)dev_counts,
+                     (hipStream_t)stream, w);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cube_abi_version(void) { return CUBE_ABI_VERSION; }
+
+const char *cube_last_error(void) { return g_err.c_str(); }
+
+int cube_stats(const float *ptr, int64_t nx, int64_t ny, int64_t nz, const int64_t *stride,
+               cube_stats_t *out)
+{
+    g_err.clear();
+    const int64_t dims[5] = {nx, ny, nz, stride ? stride[0] : 0, stride ? stride[1] : 0};
+    return run_sync(OP_STATS, ptr, dims, 0.f, 0.f, 1, out, nullptr);
+}
+
+int cube_hist(const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
+              uint64_t *counts)
+{
+    g_err.clear();
+    return run_sync(OP_HIST, ptr, dims, lo, hi, nbins, nullptr, counts);
+}
+
+int cube_stats_hist(const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
+                    cube_stats_t *out, uint64_t *counts)
+{
+    g_err.clear();
+    return run_sync(OP_FUSED, ptr, dims, lo, hi, nbins, out, counts);
+}
+
+int cube_stats_hist_minmax(const float *ptr, const int64_t *dims, int32_t nbins,
+                           cube_stats_t *out, uint64_t *counts)
+{
+    g_err.clear();
+    return run_sync(OP_MINMAX, ptr, dims, 0.f, 0.f, nbins, out, counts);
+}
+
+int cube_stats_async(const float *ptr, const int64_t *dims, cube_stats_t *dev_out,
+                     void *stream)
+{
+    g_err.clear();
+    return run_async_entry(OP_STATS, ptr, dims, 0.f, 0.f, 1, dev_out, nullptr, stream);
+}
+
+int cube_hist_async(const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
+                    uint64_t *dev_counts, void *stream)
+{
+    g_err.clear();
+    return run_async_entry(OP_HIST, ptr, dims, lo, hi, nbins, nullptr, dev_counts, stream);
+}
+
+int cube_stats_hist_async(const float *ptr, const int64_t *dims, float lo, float hi,
+                          int32_t nbins, cube_stats_t *dev_out, uint64_t *dev_counts,
+                          void *stream)
+{
+    g_err.clear();
+    return run_async_entry(OP_FUSED, ptr, dims, lo, hi, nbins, dev_out, dev_counts, stream);
+}
+
+int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims, int32_t nbins,
+                                 cube_stats_t *dev_out, uint64_t *dev_counts, void *stream)
+{
+    g_err.clear();
+    return run_async_entry(OP_MINMAX, ptr, dims, 0.f, 0.f, nbins, dev_out, dev_counts, stream);
+}
+
+int cube_set_accum_mode(int32_t mode)
+{
+    if (mode != CUBE_ACCUM_FP64MERGE && mode != CUBE_ACCUM_KAHAN32 && mode != CUBE_ACCUM_NAIVE32)
+        return fail(CUBE_EINVAL, "unknown accumulation mode %d", mode);
+    return g_accum.exchange(mode);
+}
+
+int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies)
+{
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(CUBE_EINVAL, "threads must be 0, 256, 512 or 1024");
+    if (blocks < 0 || blocks > MAX_BLOCKS) return fail(CUBE_EINVAL, "blocks outside [0, 4096]");
+    if (hist_copies < 0 || hist_copies > 32 || (hist_copies & (hist_copies - 1)))
+        return fail(CUBE_EINVAL, "hist_copies must be 0 or a power of two <= 32");
+    g_threads = threads;
+    g_blocks = blocks;
+    g_copies = hist_copies;
+    return CUBE_OK;
+}
+
+void cube_shutdown(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_ws) free_ws(kv.second);
+    g_ws.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// cube_internal.h -- structures shared by the kernels and the C-ABI layer of
+// the cube statistics library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cubestats.h"
+
+namespace cube {
+
+// One partial result per wavefront (the local stage of the paper's two-stage
+// gather, Section 2).  Moments are FP32 double-float pairs relative to the
+// wavefront's pivot K; in the naive mode K = 0 and the lo parts are 0.
+struct alignas(16) WaveRec {
+    float K, s1h, s1l, s2h, s2l, mn, mx, pad;
+    unsigned long long n_valid, below, above, pad2;
+};
+static_assert(sizeof(WaveRec) == 64, "WaveRec is 64 bytes");
+
+// A histogram range as the kernels use it.  ok: 1 valid, 0 invalid range,
+// 2 no valid voxel (the two-pass range of an all-blank box).
+struct HistRange {
+    float lo, hi, scale;
+    int32_t ok;
+};
+
+// A box after merging contiguous axes: rows of `row_len` contiguous floats,
+// row (y, z) starting at ptr + y*sy + z*sz.  Rows are cut into `segs`
+// segments of `seg_len` floats (seg_len a multiple of 4); a unit of work is
+// one segment of one row, numbered u = (z*ny + y)*segs + s.
+struct Geom {
+    const float *ptr;
+    int64_t row_len, ny, nz, sy, sz;
+    int64_t seg_len, segs, n_units;
+    uint64_t n_total;
+};
+
+enum : int32_t { HIST_NONE = 0, HIST_LDS = 1, HIST_GLOBAL = 2 };
+
+struct PassArgs {
+    Geom g;
+    int32_t nbins;
+    int32_t copies_log2;         // LDS sub-histogram copies = 1 << copies_log2
+    HistRange range;             // the given range (when dev_range is null)
+    const HistRange *dev_range;  // range formed on the device by a stats pass
+    WaveRec *recs;               // gridDim.x * waves-per-block records
+    unsigned int *ticket;        // last-block-done counter, 0 between launches
+    unsigned long long *hist_acc;// nbins global accumulators, 0 between launches
+    cube_stats_t *out;           // device result (stats passes)
+    unsigned long long *counts;  // device counts, nbins + 3 (histogram passes)
+    HistRange *out_range;        // device [min, max] range (two-pass pass 1)
+    int32_t accum_mode;          // CUBE_ACCUM_*
+    int32_t want_range;          // pass 1 of a two-pass call: write out_range
+};
+
+// Kernel launchers (cube_kernels.hip).  `stats`: compute the statistics;
+// `hist`: HIST_NONE / HIST_LDS / HIST_GLOBAL.  Returns the launch error.
+hipError_t launch_pass(const PassArgs &a, bool stats, int hist, int threads,
+                       int blocks, size_t lds_bytes, hipStream_t s);
+
+// Dynamic LDS bytes a pass needs.
+size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int threads);
+
+// Occupancy of one pass configuration: resident blocks per CU.
+int pass_blocks_per_cu(bool stats, int hist, int threads, size_t lds_bytes);
+
+}  // namespace cube

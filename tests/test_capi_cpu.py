@@ -1,0 +1,102 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol the header declares, and rejects bad arguments before any HIP call."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1111_6661_amd as cs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cubestats.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cube_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cs.load()
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), f"{n} is declared in cubestats.h but not exported"
+
+
+def test_abi_version_matches_header():
+    m = re.search(r"#define CUBE_ABI_VERSION (\d+)", open(HEADER).read())
+    assert cs.load().cube_abi_version() == int(m.group(1))
+
+
+def test_stats_struct_layout_matches_header():
+    text = open(HEADER).read()
+    assert "} cube_stats_t; /* 64 bytes */" in text
+    assert C.sizeof(cs.cube_stats_t) == 64
+    fields = [f[0] for f in cs.cube_stats_t._fields_]
+    assert fields == ["n_total", "n_valid", "n_nan", "min", "max", "mean", "m2", "std",
+                      "flags", "reserved"]
+
+
+def _code(fn, *a):
+    try:
+        fn(*a)
+    except cs.CubeError as e:
+        return e.code, str(e)
+    return 0, ""
+
+
+@pytest.mark.parametrize("lo,hi,nbins,why", [
+    (0.0, 1.0, 0, "nbins"), (0.0, 1.0, 65537, "nbins"), (math.nan, 1.0, 16, "NaN"),
+    (0.0, math.nan, 16, "NaN"), (2.0, 1.0, 16, "hi < lo"), (-math.inf, 1.0, 16, "infinite"),
+    (0.0, math.inf, 16, "infinite"), (-3e38, 3e38, 16, "overflows"), (0.0, 1e-45, 256, "narrow"),
+])
+def test_bad_ranges_rejected_before_gpu(lo, hi, nbins, why):
+    code, msg = _code(cs.cube_hist, 0x1000, [4, 4, 4, 0, 0], lo, hi, nbins)
+    assert code == cs.CUBE_EINVAL and why in msg
+    code, msg = _code(cs.cube_stats_hist, 0x1000, [4, 4, 4, 0, 0], lo, hi, nbins)
+    assert code == cs.CUBE_EINVAL and why in msg
+
+
+@pytest.mark.parametrize("dims,why", [
+    ([-1, 4, 4, 0, 0], "negative"), ([8, 4, 4, 7, 0], "row pitch"),
+    ([8, 4, 4, 8, 20], "plane pitch"), ([1 << 41, 1, 1, 0, 0], "too large"),
+])
+def test_bad_shapes_rejected_before_gpu(dims, why):
+    code, msg = _code(cs.cube_hist, 0x1000, dims, 0.0, 1.0, 8)
+    assert code == cs.CUBE_EINVAL and why in msg
+
+
+def test_bad_pointers_rejected_before_gpu():
+    code, msg = _code(cs.cube_stats, 0, 4, 4, 4)
+    assert code == cs.CUBE_EINVAL and "NULL" in msg
+    code, msg = _code(cs.cube_stats, 0x1002, 4, 4, 4)
+    assert code == cs.CUBE_EINVAL and "aligned" in msg
+    lib = cs.load()
+    d = (C.c_int64 * 5)(4, 4, 4, 0, 0)
+    assert lib.cube_stats_hist(C.c_void_p(0x1000), d, 0.0, 1.0, 8, None, None) == cs.CUBE_EINVAL
+    assert lib.cube_hist(C.c_void_p(0x1000), None, 0.0, 1.0, 8, None) == cs.CUBE_EINVAL
+    assert lib.cube_stats_async(C.c_void_p(0x1000), d, None, None) == cs.CUBE_EINVAL
+
+
+def test_mode_and_launch_setters_validate():
+    assert _code(cs.cube_set_accum_mode, 7)[0] == cs.CUBE_EINVAL
+    assert _code(cs.cube_set_launch, 100, 0, 0)[0] == cs.CUBE_EINVAL
+    assert _code(cs.cube_set_launch, 256, 5000, 0)[0] == cs.CUBE_EINVAL
+    assert _code(cs.cube_set_launch, 256, 0, 3)[0] == cs.CUBE_EINVAL
+    prev = cs.cube_set_accum_mode(cs.CUBE_ACCUM_KAHAN32)
+    assert cs.cube_set_accum_mode(prev) == cs.CUBE_ACCUM_KAHAN32
+    cs.cube_set_launch(0, 0, 0)
+
+
+def test_binding_has_no_cpu_fallback():
+    """The tensor helpers refuse CPU tensors instead of computing on the CPU."""
+    import torch
+    with pytest.raises(ValueError):
+        cs.stats(torch.zeros(8))
+    src = open(os.path.join(ROOT, "paper_1111_6661_amd", "__init__.py")).read()
+    assert "import oracle" not in src and "from oracle" not in src

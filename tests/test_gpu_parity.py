@@ -1,0 +1,274 @@
+"""GPU library against the oracle, element by element, through the C ABI.
+
+Sizes are ones the oracle finishes in well under a second, yet span several
+main-loop tiles, ragged tails, unaligned starts and strided sub-boxes.
+Counts, n_valid/n_nan and extrema must be bit-exact; mean/std within 1e-6
+(see tests/parity.py for the exact rule).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import assert_counts_match, assert_stats_match, same_f32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import paper_1111_6661_amd as cs
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cs.load()
+    cs.cube_set_launch(0, 0, 0)
+    cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    return cs
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    import synth
+    r = synth.WORKLOADS["tiny"]
+    t = synth.cube_tensor(r, synth.BASE_SEED, device="cuda")
+    return t, t.cpu().numpy()
+
+
+def check_all(cs, t, host, nbins, what, lo=None, hi=None):
+    """stats, two-pass [min, max] histogram, fused and hist-only over a range."""
+    ref = oracle.stats(host)
+    st = cs.stats(t)
+    assert_stats_match(st, ref, what + " stats")
+    st2, c2 = cs.stats_hist_minmax(t, nbins)
+    assert_stats_match(st2, ref, what + " minmax-stats")
+    if ref.n_valid:
+        assert_counts_match(c2, oracle.hist(host, ref.min, ref.max, nbins), what + " minmax")
+    else:
+        assert c2[:nbins + 2].sum() == 0 and c2[nbins + 2] == ref.n_total
+    if lo is None:
+        if not ref.n_valid:
+            return
+        lo, hi = ref.min, ref.max
+    want = oracle.hist(host, lo, hi, nbins)
+    st3, c3 = cs.stats_hist(t, lo, hi, nbins)
+    assert_stats_match(st3, ref, what + " fused-stats")
+    assert_counts_match(c3, want, what + " fused")
+    assert_counts_match(cs.hist(t, lo, hi, nbins), want, what + " hist")
+
+
+def test_tiny_workload(cs, tiny):
+    t, host = tiny
+    ref = oracle.stats(host)
+    assert 0.005 < ref.n_nan / ref.n_total < 0.02
+    check_all(cs, t, host, 256, "tiny")
+    # a range inside the data: exercises below / above
+    lo = np.float32(ref.mean - 2 * ref.std)
+    hi = np.float32(ref.mean + 2 * ref.std)
+    check_all(cs, t, host, 256, "tiny-2sigma", float(lo), float(hi))
+    for nb in (1, 7, 64, 1000, 4096):
+        check_all(cs, t, host, nb, f"tiny-{nb}bins")
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 1, 1), (5, 7, 3), (1_000_003, 1, 1),
+                                   (257, 129, 33), (4096, 3, 5), (17, 1, 900), (63, 65, 64)])
+def test_ragged_shapes(cs, shape):
+    import synth
+    nx, ny, nz = shape
+    r = synth.WORKLOADS["tiny"].scaled(nx, ny, nz)
+    t = synth.cube_tensor(r, 1234 + nx, device="cuda")
+    check_all(cs, t, t.cpu().numpy(), 128, f"shape{shape}")
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3, 5])
+def test_unaligned_starts(cs, offset):
+    import synth
+    r = synth.WORKLOADS["tiny"].scaled(301, 17, 11)
+    flat = torch.empty(r.n + 8, dtype=torch.float32, device="cuda")
+    view = flat[offset:offset + r.n].view(r.nz, r.ny, r.nx)
+    synth.fill_device(r, 99, view.data_ptr(), device=view.device)
+    check_all(cs, view, view.cpu().numpy(), 100, f"offset{offset}")
+
+
+@pytest.mark.parametrize("box", [
+    np.s_[3:40, 5:60, 7:200], np.s_[0:64, 1:2, :], np.s_[10:11, :, 1:255],
+    np.s_[:, 3:61, 0:256], np.s_[5:60, 0:64, 33:34], np.s_[1:2, 1:2, 1:250],
+])
+def test_strided_sub_boxes(cs, box):
+    import synth
+    r = synth.WORKLOADS["tiny"].scaled(256, 64, 64)
+    big = synth.cube_tensor(r, 4242, device="cuda")
+    view = big[box]
+    check_all(cs, view, big.cpu().numpy()[box], 64, f"box{box}")
+
+
+def _dev(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def bits(u):
+    return np.array(u, dtype=np.uint32).view(np.float32)
+
+
+def test_edge_values(cs):
+    cases = {
+        "signed-zeros": np.array([0.0, -0.0, 0.0, np.nan], np.float32),
+        "only-minus-zero": np.array([-0.0, -0.0], np.float32),
+        "all-nan": np.full(1000, np.nan, np.float32),
+        "single": np.array([3.5], np.float32),
+        "constant": np.full(70001, 1e4, np.float32),
+        "subnormal": np.array([1e-45, 3e-39, 1.2e-38, 0.0, 2e-40] * 99, np.float32),
+        "nan-payloads": np.concatenate([bits([0x7F800001, 0xFFC00000, 0x7FFFFFFF, 0xFF800001]),
+                                        np.array([1.0, -2.0, 5.0], np.float32)] * 50),
+        "big-offset": (1e4 + np.random.default_rng(1).standard_normal(200_000) * 1e-3
+                       ).astype(np.float32),
+        "with-inf": np.array([1.0, np.inf, -2.0, np.nan, -np.inf, 3.0], np.float32),
+    }
+    for name, a in cases.items():
+        t = _dev(a)
+        ref = oracle.stats(a)
+        st = cs.stats(t)
+        assert_stats_match(st, ref, name)
+        if name == "subnormal":   # deviations ~1e-39: below the FP32 moment range
+            from tests.parity import moments_in_fp32_range
+            assert not moments_in_fp32_range(ref)
+        if name == "with-inf":
+            assert st.min == -np.inf and st.max == np.inf
+            c = cs.hist(t, -1.0, 2.0, 3)
+            assert_counts_match(c, oracle.hist(a, -1.0, 2.0, 3), name)
+            with pytest.raises(cs.CubeError):
+                cs.stats_hist_minmax(t, 16)   # [min, max] is not a valid range
+            continue
+        if ref.n_valid:
+            for nb in (1, 3, 256):
+                try:
+                    oracle.hist_scale(ref.min, ref.max, nb)
+                except ValueError:   # [min, max] too narrow for nb bins
+                    with pytest.raises(cs.CubeError):
+                        cs.stats_hist_minmax(t, nb)
+                    continue
+                st2, c2 = cs.stats_hist_minmax(t, nb)
+                assert_counts_match(c2, oracle.hist(a, ref.min, ref.max, nb), f"{name}-{nb}")
+        else:
+            st2, c2 = cs.stats_hist_minmax(t, 8)
+            assert st2.flags & cs.CUBE_NO_VALID
+            assert c2.tolist() == [0] * 10 + [a.size]
+    # -0 orders before +0 on the GPU too
+    st = cs.stats(_dev(np.array([0.0, -0.0], np.float32)))
+    assert same_f32(st.min, -0.0) and same_f32(st.max, 0.0)
+    # degenerate range hi == lo
+    a = np.array([2.0, 2.0, 1.0, 3.0, np.nan, 2.0], np.float32)
+    assert_counts_match(cs.hist(_dev(a), 2.0, 2.0, 4), oracle.hist(a, 2.0, 2.0, 4), "hi==lo")
+
+
+def test_subnormal_bins_not_flushed(cs):
+    # scale = 2^127 exactly: 2^-127 must land in bin 1 (a flush to zero gives 0)
+    a = np.array([2.0 ** -149, 2.0 ** -127, 3 * 2.0 ** -128, 2.0 ** -126, 2.0 ** -120],
+                 dtype=np.float32)
+    lo, hi = 0.0, float(np.float32(2.0 ** -119))
+    assert_counts_match(cs.hist(_dev(a), lo, hi, 256), oracle.hist(a, lo, hi, 256), "subnormal")
+
+
+@pytest.mark.parametrize("nbins", [2048, 32768, 65536])
+def test_large_bin_counts(cs, tiny, nbins):
+    t, host = tiny
+    ref = oracle.stats(host)
+    st, c = cs.stats_hist(t, ref.min, ref.max, nbins)
+    assert_counts_match(c, oracle.hist(host, ref.min, ref.max, nbins), f"{nbins} bins")
+    assert_stats_match(st, ref, f"{nbins} bins")
+
+
+@pytest.mark.parametrize("threads,blocks,copies", [
+    (256, 0, 0), (512, 0, 1), (1024, 0, 32), (256, 1, 4), (512, 7, 2), (1024, 300, 8),
+    (256, 4096, 16),
+])
+def test_launch_shapes_agree(cs, tiny, threads, blocks, copies):
+    t, host = tiny
+    ref = oracle.stats(host)
+    want = oracle.hist(host, ref.min, ref.max, 256)
+    cs.cube_set_launch(threads, blocks, copies)
+    try:
+        st, c = cs.stats_hist(t, ref.min, ref.max, 256)
+        st2, c2 = cs.stats_hist_minmax(t, 256)
+    finally:
+        cs.cube_set_launch(0, 0, 0)
+    assert_counts_match(c, want, "fused")
+    assert_counts_match(c2, want, "minmax")
+    assert_stats_match(st, ref, "fused")
+    assert_stats_match(st2, ref, "minmax")
+
+
+def test_deterministic(cs, tiny):
+    t, _ = tiny
+    a = [cs.stats_hist(t, -3.0, 40.0, 512) for _ in range(3)]
+    for st, c in a[1:]:
+        assert st == a[0][0]
+        assert np.array_equal(c, a[0][1])
+
+
+def test_async_matches_sync(cs, tiny):
+    t, host = tiny
+    ptr, d = cs.box_of(t)
+    s = torch.cuda.Stream()
+    out = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(256 + 3, dtype=torch.int64, device="cuda")
+    out2 = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    cnt2 = torch.zeros(256 + 3, dtype=torch.int64, device="cuda")
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        cs.cube_stats_hist_async(ptr, d, -2.0, 30.0, 256, out.data_ptr(), cnt.data_ptr(),
+                                 s.cuda_stream)
+        cs.cube_stats_hist_minmax_async(ptr, d, 256, out2.data_ptr(), cnt2.data_ptr(),
+                                        s.cuda_stream)
+    s.synchronize()
+    st = cs.Stats.from_bytes(out.cpu().numpy().tobytes())
+    ref_st, ref_c = cs.stats_hist(t, -2.0, 30.0, 256)
+    assert st == ref_st
+    assert np.array_equal(cnt.cpu().numpy().view(np.uint64), ref_c)
+    st2 = cs.Stats.from_bytes(out2.cpu().numpy().tobytes())
+    ref2 = cs.stats_hist_minmax(t, 256)
+    assert st2 == ref2[0]
+    assert np.array_equal(cnt2.cpu().numpy().view(np.uint64), ref2[1])
+
+
+def test_empty_boxes(cs):
+    t = torch.zeros(16, device="cuda")
+    for dims in ([0, 4, 4, 0, 0], [4, 0, 4, 0, 0], [4, 4, 0, 0, 0]):
+        st, c = cs.cube_stats_hist(t.data_ptr(), dims, 0.0, 1.0, 8)
+        assert st.n_total == 0 and st.flags & cs.CUBE_NO_VALID and math.isnan(st.mean)
+        assert c.tolist() == [0] * 11
+
+
+def test_device_side_pointer_checks(cs):
+    host = np.zeros(1024, np.float32)
+    with pytest.raises(cs.CubeError) as e:
+        cs.cube_stats(host.ctypes.data, 1024, 1, 1)
+    assert e.value.code == cs.CUBE_EINVAL
+    t = torch.zeros(1000, device="cuda")
+    # a box running past its allocation is refused before any launch
+    with pytest.raises(cs.CubeError) as e:
+        cs.cube_stats(t.data_ptr(), 1 << 30, 1, 1)
+    assert e.value.code == cs.CUBE_EINVAL
+
+
+def test_accum_modes_run_and_rank(cs):
+    """Naive FP32, Kahan FP32 and the FP64-merge path on a large-offset cube:
+    the production path meets 1e-6, the FP32-only modes are reported."""
+    import synth
+    r = synth.WORKLOADS["stress128g"].scaled(512, 256, 64)
+    t = synth.cube_tensor(r, 77, device="cuda")
+    host = t.cpu().numpy()
+    ref = oracle.stats(host)
+    errs = {}
+    try:
+        for mode in (cs.CUBE_ACCUM_NAIVE32, cs.CUBE_ACCUM_KAHAN32, cs.CUBE_ACCUM_FP64MERGE):
+            cs.cube_set_accum_mode(mode)
+            st = cs.stats(t)
+            assert st.n_valid == ref.n_valid and same_f32(st.min, ref.min)
+            errs[mode] = abs(st.std - ref.std) / ref.std
+    finally:
+        cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    assert errs[cs.CUBE_ACCUM_FP64MERGE] <= 1e-6
+    assert errs[cs.CUBE_ACCUM_NAIVE32] > errs[cs.CUBE_ACCUM_FP64MERGE]
+    print("std rel err naive/kahan32/fp64merge:", errs)
