@@ -86,6 +86,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--launch", default="",
+                    help="threads,blocks,hist_copies,unroll override (0 = automatic)")
+    ap.add_argument("--only-fused", action="store_true",
+                    help="time the fused pass only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -101,6 +105,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.launch:
+        cs.cube_set_launch(*[int(v) for v in args.launch.split(",")])
     name = "brick16g"
     r = synth.WORKLOADS[name]
     nbins = synth.HIST_BINS[name]
@@ -148,8 +154,9 @@ def main() -> int:
 
     extra = {}
     n_short = max(5, args.steps // 2)
-    for label, fn in (("stats_only", stats_only), ("hist_only", hist_only),
-                      ("two_pass_minmax", two_pass)):
+    others = () if args.only_fused else (("stats_only", stats_only), ("hist_only", hist_only),
+                                          ("two_pass_minmax", two_pass))
+    for label, fn in others:
         w, e = time_launches(fn, stream, n_short, 2)
         extra[label] = {"ms_per_call_events": round(e, 4), "voxels_per_s": r.n / (e * 1e-3)}
         log(f"{label}: {e:.4f} ms")

@@ -63,6 +63,13 @@
 extern "C" {
 #endif
 
+/* Every entry point below is exported; the library hides everything else. */
+#if defined(__GNUC__)
+#define CUBE_API __attribute__((visibility("default")))
+#else
+#define CUBE_API
+#endif
+
 #define CUBE_ABI_VERSION 1
 
 #define CUBE_OK 0
@@ -98,25 +105,25 @@ typedef struct cube_stats_t {
 } cube_stats_t; /* 64 bytes */
 
 /* Library version; equals CUBE_ABI_VERSION of the header it was built with. */
-int cube_abi_version(void);
+CUBE_API int cube_abi_version(void);
 
 /* Text of the calling thread's last error ("" if none).  Valid until the next
  * call from the same thread. */
-const char *cube_last_error(void);
+CUBE_API const char *cube_last_error(void);
 
 /*
  * Statistics of one box in one pass (Abstract: data minimum/maximum;
  * Section 3: standard deviation).  `stride` is NULL (dense) or a HOST array
  * {sy, sz} of pitches in elements.  `out` is HOST memory.  Synchronous.
  */
-int cube_stats(const float *ptr, int64_t nx, int64_t ny, int64_t nz,
+CUBE_API int cube_stats(const float *ptr, int64_t nx, int64_t ny, int64_t nz,
                const int64_t *stride, cube_stats_t *out);
 
 /*
  * Histogram of one box over a given range (Abstract: the histogram task).
  * `counts` is HOST memory of nbins + 3 uint64.  Synchronous.
  */
-int cube_hist(const float *ptr, const int64_t *dims, float lo, float hi,
+CUBE_API int cube_hist(const float *ptr, const int64_t *dims, float lo, float hi,
               int32_t nbins, uint64_t *counts);
 
 /*
@@ -124,7 +131,7 @@ int cube_hist(const float *ptr, const int64_t *dims, float lo, float hi,
  * voxel once.  Results equal those of cube_stats and cube_hist (counts and
  * extrema bit-exact; moments within rounding).  HOST outputs.  Synchronous.
  */
-int cube_stats_hist(const float *ptr, const int64_t *dims, float lo, float hi,
+CUBE_API int cube_stats_hist(const float *ptr, const int64_t *dims, float lo, float hi,
                     int32_t nbins, cube_stats_t *out, uint64_t *counts);
 
 /*
@@ -135,19 +142,19 @@ int cube_stats_hist(const float *ptr, const int64_t *dims, float lo, float hi,
  * CUBE_HIST_BAD_RANGE) the statistics are returned, the bins are 0, and the
  * call returns CUBE_EINVAL.  HOST outputs.  Synchronous.
  */
-int cube_stats_hist_minmax(const float *ptr, const int64_t *dims, int32_t nbins,
+CUBE_API int cube_stats_hist_minmax(const float *ptr, const int64_t *dims, int32_t nbins,
                            cube_stats_t *out, uint64_t *counts);
 
 /* Stream-ordered forms of the four calls above.  `dev_out` (one
  * cube_stats_t) and `dev_counts` (nbins + 3 uint64) are DEVICE memory. */
-int cube_stats_async(const float *ptr, const int64_t *dims, cube_stats_t *dev_out,
+CUBE_API int cube_stats_async(const float *ptr, const int64_t *dims, cube_stats_t *dev_out,
                      void *stream);
-int cube_hist_async(const float *ptr, const int64_t *dims, float lo, float hi,
+CUBE_API int cube_hist_async(const float *ptr, const int64_t *dims, float lo, float hi,
                     int32_t nbins, uint64_t *dev_counts, void *stream);
-int cube_stats_hist_async(const float *ptr, const int64_t *dims, float lo,
+CUBE_API int cube_stats_hist_async(const float *ptr, const int64_t *dims, float lo,
                           float hi, int32_t nbins, cube_stats_t *dev_out,
                           uint64_t *dev_counts, void *stream);
-int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims,
+CUBE_API int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims,
                                  int32_t nbins, cube_stats_t *dev_out,
                                  uint64_t *dev_counts, void *stream);
 
@@ -157,19 +164,111 @@ int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims,
  * the 1e-6 relative bound on hard inputs).  Returns the previous mode, or
  * CUBE_EINVAL for an unknown mode.
  */
-int cube_set_accum_mode(int32_t mode);
+CUBE_API int cube_set_accum_mode(int32_t mode);
 
 /*
  * Launch-shape override for the single-box calls, used by the autotuner and
  * for experiments: threads per block (256, 512 or 1024; 0 = automatic),
  * blocks per launch (0 = automatic), histogram sub-copies per block (1..32,
- * a power of two; 0 = automatic).  Applies to later calls from any thread.
+ * a power of two; 0 = automatic), float4 loads per lane per pipelined tile
+ * (2, 4 or 8; 0 = automatic).  Applies to later calls from any thread.
+ * Results do not depend on the launch shape except for the rounding of the
+ * moments (the merge order follows the grid).
  */
-int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies);
+CUBE_API int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll);
 
 /* Release every workspace on every device (synchronises each stream that
  * owns one).  The library stays usable; workspaces are made again on demand. */
-void cube_shutdown(void);
+CUBE_API void cube_shutdown(void);
+
+/* ------------------------------------------------------------------------
+ * Batched queries in one persistent launch (the paper's batched analysis
+ * service, Abstract; many sub-cubes of one dataset, Section 3).
+ * ------------------------------------------------------------------------ */
+
+#define CUBE_Q_STATS 0  /* statistics                                       */
+#define CUBE_Q_HIST 1   /* histogram over [lo, hi]                           */
+#define CUBE_Q_FUSED 2  /* statistics + histogram over [lo, hi], one read   */
+#define CUBE_Q_MINMAX 3 /* statistics, then histogram over the box's [min, max] */
+
+typedef struct cube_query_t {
+    const float *ptr;   /* DEVICE data, 4-byte aligned (same rules as above) */
+    int64_t dims[5];    /* nx, ny, nz, sy, sz (0 pitch = dense)              */
+    int32_t kind;       /* CUBE_Q_*                                          */
+    int32_t nbins;      /* histogram kinds: 1..32768                         */
+    float lo, hi;       /* CUBE_Q_HIST, CUBE_Q_FUSED                         */
+    cube_stats_t *out;  /* DEVICE, one cube_stats_t (kinds with statistics)  */
+    uint64_t *counts;   /* DEVICE, nbins + 3 (kinds with a histogram)        */
+} cube_query_t;
+
+/* An opaque batch: device work-list buffers, grown on demand and reused.
+ * One batch runs one work list at a time; use several batches (one per
+ * stream) to overlap batches on the device. */
+typedef struct cube_batch cube_batch_t;
+
+CUBE_API int cube_batch_create(cube_batch_t **out);
+/* Waits for the batch's last launch, then frees everything. */
+CUBE_API void cube_batch_destroy(cube_batch_t *b);
+/* Tile size in voxels (4096..2^30; default 2^20) and threads per block (0 =
+ * automatic) for later enqueues.  A query's results depend only on its own
+ * data and the tile size, not on the other queries of the batch. */
+CUBE_API int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads);
+/* Validate the n queries (every check of the single-box calls, on the
+ * host), build the work list, copy it to the device and launch, all on
+ * `stream` (a hipStream_t).  Results are valid when the stream reaches this
+ * point.  Each query's results are the same as those of the matching
+ * single-box call, except for the rounding of mean and m2 (the tiling
+ * differs); counts and extrema are bit-exact. */
+CUBE_API int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *stream);
+/* Launch the last enqueued work list again (no host work, no copies). */
+CUBE_API int cube_batch_relaunch(cube_batch_t *b, void *stream);
+/* Same as cube_batch_relaunch through a captured HIP graph: the first call
+ * per stream captures the launch, later calls replay it. */
+CUBE_API int cube_batch_graph_launch(cube_batch_t *b, void *stream);
+/* Wait for the batch and report whether every two-pass query completed
+ * (CUBE_EDEVICE if a query's bounded wait for its range expired). */
+CUBE_API int cube_batch_check(cube_batch_t *b);
+/* Synchronous convenience: create, enqueue on the default stream, check,
+ * destroy. */
+CUBE_API int cube_batch_run(const cube_query_t *q, int32_t n);
+
+/* ------------------------------------------------------------------------
+ * Query server over cubes resident in GPU memory (the paper's analysis as a
+ * service for many users, with batched and real-time requests: Abstract,
+ * Sections 2 and 3).  Continuous batching: a worker thread forms batches of
+ * waiting queries whenever one of `slots` streams is free and the device
+ * scratch in flight stays within `max_inflight_bytes`, and launches each
+ * batch as one persistent launch, so batches overlap on the device.
+ * CUBE_SERVE_PLAIN instead runs one query at a time, in arrival order,
+ * through the single-box entry points (the baseline).
+ * ------------------------------------------------------------------------ */
+
+#define CUBE_SERVE_BATCHED 0
+#define CUBE_SERVE_PLAIN 1
+
+typedef struct cube_server cube_server_t;
+
+/* slots: 1..16 concurrent batches; max_batch: queries per batch (1..4096);
+ * max_inflight_bytes: device scratch budget (>= 4096); tile_voxels: 0 =
+ * 2^20, else 4096..2^30.  The calling thread's current device is used. */
+CUBE_API int cube_server_create(int32_t mode, int32_t slots, int32_t max_batch,
+                                int64_t max_inflight_bytes, int64_t tile_voxels,
+                                cube_server_t **out);
+/* Queue one query (host-side checks now; CUBE_EBUSY when the queue is full).
+ * The query's device outputs must stay valid until it completes.  Returns
+ * its id in *id.  Thread-safe. */
+CUBE_API int cube_server_submit(cube_server_t *s, const cube_query_t *q, uint64_t *id);
+/* Wait up to timeout_s (< 0: no limit) for query `id`; on completion its
+ * outputs are valid, the latency from submission to completion is stored
+ * in *latency_s, and the id is retired.  CUBE_EBUSY on timeout (the id stays
+ * valid); the query's own error code if it failed. */
+CUBE_API int cube_server_wait(cube_server_t *s, uint64_t id, double timeout_s, double *latency_s);
+/* Latency percentiles (seconds) over the queries completed so far;
+ * `reset` != 0 clears the record. */
+CUBE_API int cube_server_latency(cube_server_t *s, double *p50_s, double *p99_s,
+                                 uint64_t *n_done, int32_t reset);
+/* Finish the queued and running queries, then stop and free the server. */
+CUBE_API void cube_server_destroy(cube_server_t *s);
 
 #ifdef __cplusplus
 }

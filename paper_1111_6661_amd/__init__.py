@@ -45,6 +45,14 @@ class cube_stats_t(C.Structure):
 
 assert C.sizeof(cube_stats_t) == 64
 
+CUBE_Q_STATS, CUBE_Q_HIST, CUBE_Q_FUSED, CUBE_Q_MINMAX = 0, 1, 2, 3
+
+
+class cube_query_t(C.Structure):
+    _fields_ = [("ptr", C.c_void_p), ("dims", C.c_int64 * 5), ("kind", C.c_int32),
+                ("nbins", C.c_int32), ("lo", C.c_float), ("hi", C.c_float),
+                ("out", C.c_void_p), ("counts", C.c_void_p)]
+
 
 @dataclass
 class Stats:
@@ -92,8 +100,31 @@ def load() -> C.CDLL:
     lib.cube_stats_hist_async.argtypes = [P, I64P, f32, f32, i32, P, P, P]
     lib.cube_stats_hist_minmax_async.argtypes = [P, I64P, i32, P, P, P]
     lib.cube_set_accum_mode.argtypes = [i32]
-    lib.cube_set_launch.argtypes = [i32, i32, i32]
+    lib.cube_set_launch.argtypes = [i32, i32, i32, i32]
     lib.cube_shutdown.restype = None
+    lib.cube_batch_create.argtypes = [C.POINTER(C.c_void_p)]
+    lib.cube_batch_destroy.argtypes = [P]
+    lib.cube_batch_destroy.restype = None
+    lib.cube_batch_set_tile.argtypes = [P, i64, i32]
+    lib.cube_batch_enqueue.argtypes = [P, C.POINTER(cube_query_t), i32, P]
+    lib.cube_batch_relaunch.argtypes = [P, P]
+    lib.cube_batch_graph_launch.argtypes = [P, P]
+    lib.cube_batch_check.argtypes = [P]
+    lib.cube_batch_run.argtypes = [C.POINTER(cube_query_t), i32]
+    lib.cube_server_create.argtypes = [i32, i32, i32, i64, i64, C.POINTER(C.c_void_p)]
+    lib.cube_server_submit.argtypes = [P, C.POINTER(cube_query_t), C.POINTER(C.c_uint64)]
+    lib.cube_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_double)]
+    lib.cube_server_latency.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_uint64), i32]
+    lib.cube_server_destroy.argtypes = [P]
+    lib.cube_server_destroy.restype = None
+    for name in ("cube_server_create", "cube_server_submit", "cube_server_wait",
+                 "cube_server_latency"):
+        getattr(lib, name).restype = C.c_int
+    for name in ("cube_batch_create", "cube_batch_set_tile", "cube_batch_enqueue",
+                 "cube_batch_relaunch", "cube_batch_graph_launch", "cube_batch_check",
+                 "cube_batch_run"):
+        getattr(lib, name).restype = C.c_int
     for name in ("cube_stats", "cube_hist", "cube_stats_hist", "cube_stats_hist_minmax",
                  "cube_stats_async", "cube_hist_async", "cube_stats_hist_async",
                  "cube_stats_hist_minmax_async", "cube_set_accum_mode", "cube_set_launch"):
@@ -178,8 +209,9 @@ def cube_set_accum_mode(mode: int) -> int:
     return _check(load().cube_set_accum_mode(mode))
 
 
-def cube_set_launch(threads: int = 0, blocks: int = 0, hist_copies: int = 0) -> None:
-    _check(load().cube_set_launch(threads, blocks, hist_copies))
+def cube_set_launch(threads: int = 0, blocks: int = 0, hist_copies: int = 0,
+                    unroll: int = 0) -> None:
+    _check(load().cube_set_launch(threads, blocks, hist_copies, unroll))
 
 
 def cube_shutdown() -> None:
@@ -225,3 +257,99 @@ def stats_hist(t, lo: float, hi: float, nbins: int):
 def stats_hist_minmax(t, nbins: int):
     ptr, d = box_of(t)
     return cube_stats_hist_minmax(ptr, d, nbins)
+
+
+# ------------------------------------------------------------------ batches
+def make_query(ptr: int, dims, kind: int, nbins: int = 0, lo: float = 0.0, hi: float = 0.0,
+               out: int = 0, counts: int = 0) -> cube_query_t:
+    q = cube_query_t()
+    q.ptr = ptr
+    d = list(dims) + [0] * (5 - len(dims))
+    for i in range(5):
+        q.dims[i] = d[i]
+    q.kind, q.nbins, q.lo, q.hi = kind, nbins, lo, hi
+    q.out, q.counts = out or None, counts or None
+    return q
+
+
+class Batch:
+    """A reusable batch (cube_batch_t): enqueue a list of cube_query_t, then
+    relaunch or graph-launch it.  Outputs are the device pointers in the
+    queries."""
+
+    def __init__(self, tile_voxels: int = 0, threads: int = 0):
+        self._h = C.c_void_p()
+        _check(load().cube_batch_create(C.byref(self._h)))
+        if tile_voxels or threads:
+            _check(load().cube_batch_set_tile(self._h, tile_voxels or (1 << 20), threads))
+
+    def enqueue(self, queries, stream: int = 0) -> None:
+        arr = (cube_query_t * len(queries))(*queries)
+        self._keep = arr
+        _check(load().cube_batch_enqueue(self._h, arr, len(queries), C.c_void_p(stream)))
+
+    def relaunch(self, stream: int = 0) -> None:
+        _check(load().cube_batch_relaunch(self._h, C.c_void_p(stream)))
+
+    def graph_launch(self, stream: int = 0) -> None:
+        _check(load().cube_batch_graph_launch(self._h, C.c_void_p(stream)))
+
+    def check(self) -> None:
+        _check(load().cube_batch_check(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            load().cube_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cube_batch_run(queries) -> None:
+    arr = (cube_query_t * len(queries))(*queries)
+    _check(load().cube_batch_run(arr, len(queries)))
+
+
+# ------------------------------------------------------------------ server
+CUBE_SERVE_BATCHED, CUBE_SERVE_PLAIN = 0, 1
+
+
+class Server:
+    """cube_server_t: submit queries from any thread, wait for each."""
+
+    def __init__(self, mode: int = CUBE_SERVE_BATCHED, slots: int = 4, max_batch: int = 64,
+                 max_inflight_bytes: int = 1 << 30, tile_voxels: int = 0):
+        self._h = C.c_void_p()
+        _check(load().cube_server_create(mode, slots, max_batch, max_inflight_bytes,
+                                         tile_voxels, C.byref(self._h)))
+
+    def submit(self, q: cube_query_t) -> int:
+        i = C.c_uint64()
+        _check(load().cube_server_submit(self._h, C.byref(q), C.byref(i)))
+        return i.value
+
+    def wait(self, qid: int, timeout_s: float = -1.0) -> float:
+        lat = C.c_double()
+        _check(load().cube_server_wait(self._h, qid, timeout_s, C.byref(lat)))
+        return lat.value
+
+    def latency(self, reset: bool = False):
+        p50, p99, n = C.c_double(), C.c_double(), C.c_uint64()
+        _check(load().cube_server_latency(self._h, C.byref(p50), C.byref(p99), C.byref(n),
+                                          1 if reset else 0))
+        return p50.value, p99.value, n.value
+
+    def close(self) -> None:
+        if self._h:
+            load().cube_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,14 +8,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcubestats.so")
-SOURCES = ["cube_kernels.hip", "cube_capi.hip"]
+SOURCES = ["cube_kernels.hip", "cube_capi.hip", "cube_batch.hip", "cube_server.hip"]
 
 # -packed-fp32-ops: no packed FP32 instructions are emitted (the kernels are
 # written for scalar FP32 VALU operations only).  -ffp-contract=off: no
 # multiply-add contraction other than the explicit fmaf calls; denormals are
 # kept (no -fgpu-flush-denormals-to-zero).
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
-               "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
+               "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero", "-fvisibility=hidden",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-result", "-Wno-unused-value"]
 

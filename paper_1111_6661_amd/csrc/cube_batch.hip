@@ -1,0 +1,579 @@
+// cube_batch.hip -- many boxes (queries) in one persistent launch.
+//
+// The host cuts every query into tiles (contiguous ranges of its work units)
+// and lists them: first the tiles of every query's first phase (statistics,
+// fused statistics + histogram, or a histogram over a given range), then the
+// second-phase tiles of the two-pass queries (the histogram over the query's
+// own [min, max]).  A grid sized to the GPU's occupancy pulls tiles from one
+// atomic counter until the list is exhausted.  Per tile, a block scans the
+// units (the same device code as the single-box pass), writes one record per
+// wavefront into the query's record range and flushes its LDS histogram into
+// the query's accumulators.  The block that finishes a query's last tile of
+// a phase merges that query's records in tile order (FP64) and writes its
+// results; for a two-pass query it also publishes the [min, max] range, which
+// releases the query's second-phase tiles.  This is the paper's batched
+// service (Abstract) and its sub-cube processing (Section 3) on one GPU.
+//
+// Progress: a second-phase tile waits only for its own query's first phase,
+// whose tiles all come earlier in the list and were therefore taken by
+// running blocks that never wait; the wait is bounded anyway (an error flag
+// is raised and the tile skipped if it ever expires).  Results of a query do
+// not depend on the other queries of the batch (its tiling and merge order
+// are its own), so a query gives the same bits alone and in any mix.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "cube_device.h"
+
+namespace cube {
+
+enum : int32_t { BQ_STATS = CUBE_Q_STATS, BQ_HIST = CUBE_Q_HIST, BQ_FUSED = CUBE_Q_FUSED,
+                 BQ_MINMAX = CUBE_Q_MINMAX };
+
+struct BatchItem {                 // read-only during a launch
+    Geom g;
+    int32_t kind, nbins;
+    HistRange range;               // given range (HIST, FUSED)
+    int32_t ntiles1, ntiles2;      // tiles of phase 1 / phase 2
+    long long units_per_tile;
+    long long rec1, rec2;          // first record of each phase
+    long long acc0;                // first histogram accumulator
+    cube_stats_t *out;
+    unsigned long long *counts;
+};
+
+struct BatchState {                // zero between launches
+    unsigned int done1, done2, ready, pad;
+    HistRange range;
+};
+
+struct BatchTile {
+    int32_t item, phase;
+    int32_t local, pad;            // tile index within the item's phase
+};
+
+struct BatchArgs {
+    const BatchItem *items;
+    BatchState *state;
+    const BatchTile *tiles;
+    int32_t n_tiles, copies_log2;
+    WaveRec *recs;
+    unsigned long long *acc;
+    unsigned int *ctl;             // [0] next tile, [1] exit ticket, [2] error flag
+    int32_t accum_mode;
+    unsigned int spin_limit;
+};
+
+constexpr int BATCH_UNROLL = 4;
+
+template <bool STATS, int HIST>
+__device__ void batch_scan(const BatchItem &it, long long u0, long long u1, Lane &L, Wave &W,
+                           const Hist &H)
+{
+    scan_units<STATS, HIST, CUBE_ACCUM_FP64MERGE, BATCH_UNROLL>(it.g, u0, u1, L, W, H);
+}
+
+__global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
+{
+    extern __shared__ unsigned int lds[];
+    __shared__ int s_tile;
+    __shared__ unsigned int s_flag;
+    __shared__ HistRange s_range;
+    const int tid = threadIdx.x, wid = tid >> 6, nw = blockDim.x >> 6;
+
+    while (true) {
+        if (tid == 0) s_tile = (int)atomicAdd(&a.ctl[0], 1u);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= a.n_tiles) break;
+        const BatchTile tile = a.tiles[t];
+        const BatchItem &it = a.items[tile.item];
+        BatchState *st = &a.state[tile.item];
+        const long long u0 = (long long)tile.local * it.units_per_tile;
+        const long long u1 = min(u0 + it.units_per_tile, it.g.n_units);
+        unsigned long long *acc = a.acc + it.acc0;
+
+        // The histogram range of this tile.
+        HistRange range = it.range;
+        bool skip = false;
+        if (tile.phase == 2) {
+            if (tid == 0) {
+                unsigned int spins = 0;
+                s_flag = 1u;
+                while (__hip_atomic_load(&st->ready, __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                    __builtin_amdgcn_s_sleep(8);
+                    if (++spins > a.spin_limit) {
+                        atomicOr(&a.ctl[2], 1u);
+                        s_flag = 0u;
+                        break;
+                    }
+                }
+                if (s_flag) s_range = st->range;
+            }
+            __syncthreads();
+            skip = s_flag == 0u;
+            range = s_range;
+        }
+        const bool stats = tile.phase == 1 && it.kind != BQ_HIST;
+        const bool hist = tile.phase == 2 || it.kind == BQ_HIST || it.kind == BQ_FUSED;
+
+        Hist H;
+        const bool hist_on = hist_setup(H, range, it.nbins, a.copies_log2, lds, acc);
+        Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f};
+        Wave W = {0.f, 0, 0ull, 0ull, 0ull, 0ull};
+        if (hist) lds_zero(lds, it.nbins, a.copies_log2);
+        if (!skip) {
+            if (stats && hist)
+                batch_scan<true, HIST_LDS>(it, u0, u1, L, W, H);
+            else if (stats)
+                batch_scan<true, HIST_NONE>(it, u0, u1, L, W, H);
+            else
+                batch_scan<false, HIST_LDS>(it, u0, u1, L, W, H);
+        }
+        const long long rec0 = tile.phase == 1 ? it.rec1 : it.rec2;
+        WaveRec *recs = a.recs + rec0;
+        if (stats)
+            write_wave_record<true, CUBE_ACCUM_FP64MERGE>(L, W, &recs[(long long)tile.local * nw + wid]);
+        else
+            write_wave_record<false, CUBE_ACCUM_FP64MERGE>(L, W, &recs[(long long)tile.local * nw + wid]);
+        if (hist) hist_flush(lds, it.nbins, a.copies_log2, acc);
+
+        // Completion of the query's phase: the last tile merges.
+        __threadfence();
+        __syncthreads();
+        const int ntiles = tile.phase == 1 ? it.ntiles1 : it.ntiles2;
+        if (tid == 0) {
+            unsigned int *done = tile.phase == 1 ? &st->done1 : &st->done2;
+            s_flag = atomicAdd(done, 1u) == (unsigned int)(ntiles - 1);
+        }
+        __syncthreads();
+        if (s_flag) {
+            __threadfence();
+            const int n_recs = ntiles * nw;
+            unsigned long long nv, below, above;
+            if (stats) {
+                finish_stats<CUBE_ACCUM_FP64MERGE>(recs, n_recs, a.accum_mode, it.g.n_total,
+                                                   it.out, it.kind == BQ_MINMAX ? &st->range
+                                                                                : nullptr,
+                                                   it.nbins, nv, below, above);
+            } else {
+                const Summary<float> S = merge_records<float, CUBE_ACCUM_KAHAN32>(recs, n_recs);
+                nv = S.nv;
+                below = S.below;
+                above = S.above;
+            }
+            if (hist)
+                finish_hist(acc, it.counts, it.nbins, hist_on, below, above,
+                            it.g.n_total - nv);
+            if (tid == 0) {
+                if (tile.phase == 1) {
+                    st->done1 = 0u;
+                    if (it.kind == BQ_MINMAX) {
+                        __threadfence();
+                        __hip_atomic_store(&st->ready, 1u, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                } else {
+                    // Every second-phase tile of this query has read the
+                    // range: the query's state returns to zero.
+                    st->done2 = 0u;
+                    st->ready = 0u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // The last block to leave returns the work counters to zero.
+    __threadfence();
+    if (tid == 0 && atomicAdd(&a.ctl[1], 1u) == gridDim.x - 1) {
+        a.ctl[0] = 0u;
+        a.ctl[1] = 0u;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+static hipError_t batch_occupancy(int threads, size_t lds, int *bpc)
+{
+    const void *k = reinterpret_cast<const void *>(&k_batch);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k, threads, lds);
+}
+
+}  // namespace cube
+
+using namespace cube;
+
+// The batch object: device buffers sized for the largest batch seen so far,
+// pinned staging for the work list, and a captured graph per stream.
+struct cube_batch {
+    std::mutex mu;
+    int device = 0;
+    // capacities
+    size_t cap_items = 0, cap_tiles = 0, cap_recs = 0, cap_acc = 0;
+    BatchItem *d_items = nullptr;
+    BatchState *d_state = nullptr;
+    BatchTile *d_tiles = nullptr;
+    WaveRec *d_recs = nullptr;
+    unsigned long long *d_acc = nullptr;
+    unsigned int *d_ctl = nullptr;
+    BatchItem *h_items = nullptr;   // pinned
+    BatchTile *h_tiles = nullptr;   // pinned
+    hipStream_t last_stream = nullptr;
+    hipEvent_t staged = nullptr;    // the last work-list copy has been read
+    bool have_work = false;
+    BatchArgs args;
+    int threads = 512, blocks = 0;
+    size_t lds = 0;
+    long long tile_voxels = 1 << 20;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+namespace {
+
+void drop_graph(cube_batch *b)
+{
+    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+    b->graph_stream = nullptr;
+}
+
+void free_buffers(cube_batch *b)
+{
+    if (b->last_stream || b->have_work) hipStreamSynchronize(b->last_stream);
+    hipFree(b->d_items);
+    hipFree(b->d_state);
+    hipFree(b->d_tiles);
+    hipFree(b->d_recs);
+    hipFree(b->d_acc);
+    hipFree(b->d_ctl);
+    hipHostFree(b->h_items);
+    hipHostFree(b->h_tiles);
+    b->d_items = nullptr;
+    b->d_state = nullptr;
+    b->d_tiles = nullptr;
+    b->d_recs = nullptr;
+    b->d_acc = nullptr;
+    b->d_ctl = nullptr;
+    b->h_items = nullptr;
+    b->h_tiles = nullptr;
+    b->cap_items = b->cap_tiles = b->cap_recs = b->cap_acc = 0;
+}
+
+// Grow the buffers to hold the given sizes (waits for the previous launch;
+// new state / accumulators / counters are zeroed).
+int ensure(cube_batch *b, size_t items, size_t tiles, size_t recs, size_t acc)
+{
+    if (items <= b->cap_items && tiles <= b->cap_tiles && recs <= b->cap_recs &&
+        acc <= b->cap_acc)
+        return CUBE_OK;
+    drop_graph(b);
+    free_buffers(b);
+    items = items < 64 ? 64 : items * 3 / 2;
+    tiles = tiles < 1024 ? 1024 : tiles * 3 / 2;
+    recs = recs < 4096 ? 4096 : recs * 3 / 2;
+    acc = acc < 4096 ? 4096 : acc * 3 / 2;
+    bool ok = hipMalloc(&b->d_items, items * sizeof(BatchItem)) == hipSuccess &&
+              hipMalloc(&b->d_state, items * sizeof(BatchState)) == hipSuccess &&
+              hipMalloc(&b->d_tiles, tiles * sizeof(BatchTile)) == hipSuccess &&
+              hipMalloc(&b->d_recs, recs * sizeof(WaveRec)) == hipSuccess &&
+              hipMalloc(&b->d_acc, acc * 8) == hipSuccess &&
+              hipMalloc(&b->d_ctl, 256) == hipSuccess &&
+              hipHostMalloc(&b->h_items, items * sizeof(BatchItem)) == hipSuccess &&
+              hipHostMalloc(&b->h_tiles, tiles * sizeof(BatchTile)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_buffers(b);
+        return fail(CUBE_ENOMEM, "batch buffer allocation failed");
+    }
+    hipError_t e;
+    if ((e = hipMemset(b->d_state, 0, items * sizeof(BatchState))) != hipSuccess ||
+        (e = hipMemset(b->d_acc, 0, acc * 8)) != hipSuccess ||
+        (e = hipMemset(b->d_ctl, 0, 256)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        free_buffers(b);
+        return hip_fail(e, "batch buffer initialisation");
+    }
+    b->cap_items = items;
+    b->cap_tiles = tiles;
+    b->cap_recs = recs;
+    b->cap_acc = acc;
+    return CUBE_OK;
+}
+
+int launch_batch(cube_batch *b, hipStream_t s)
+{
+    BatchArgs a = b->args;
+    void *args[] = {&a};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&k_batch), dim3(b->blocks),
+                                   dim3(b->threads), args, b->lds, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    b->last_stream = s;
+    return CUBE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cube_batch_create(cube_batch_t **out)
+{
+    if (!out) return fail(CUBE_EINVAL, "out is NULL");
+    cube_batch *b = new cube_batch;
+    hipGetDevice(&b->device);
+    *out = b;
+    return CUBE_OK;
+}
+
+void cube_batch_destroy(cube_batch_t *b)
+{
+    if (!b) return;
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        drop_graph(b);
+        free_buffers(b);
+        if (b->staged) hipEventDestroy(b->staged);
+    }
+    delete b;
+}
+
+int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads)
+{
+    if (!b) return fail(CUBE_EINVAL, "batch is NULL");
+    if (tile_voxels < 4096 || tile_voxels > ((int64_t)1 << 30))
+        return fail(CUBE_EINVAL, "tile_voxels outside [4096, 2^30]");
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(CUBE_EINVAL, "threads must be 0, 256, 512 or 1024");
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->tile_voxels = tile_voxels;
+    b->threads = threads ? threads : 512;
+    return CUBE_OK;
+}
+
+int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *stream)
+{
+    if (!b) return fail(CUBE_EINVAL, "batch is NULL");
+    if (n < 0 || (n > 0 && !q)) return fail(CUBE_EINVAL, "bad query list");
+    std::lock_guard<std::mutex> lk(b->mu);
+    hipStream_t s = (hipStream_t)stream;
+    // Validate every query and plan its tiles.
+    std::vector<BatchItem> items((size_t)n);
+    std::vector<long long> order((size_t)n);
+    size_t n_tiles = 0, n_recs = 0, n_acc = 0;
+    int max_bins = 1;
+    const int nw = b->threads / 64;
+    for (int i = 0; i < n; ++i) {
+        const cube_query_t &qq = q[i];
+        Box box;
+        int rc = check_box(qq.ptr, qq.dims, &box);
+        if (!rc) rc = check_box_device(&box);
+        if (rc) return fail(rc, "query %d: %s", i, cube_last_error());
+        BatchItem &it = items[(size_t)i];
+        memset(&it, 0, sizeof it);
+        it.kind = qq.kind;
+        it.nbins = qq.nbins;
+        if (qq.kind < CUBE_Q_STATS || qq.kind > CUBE_Q_MINMAX)
+            return fail(CUBE_EINVAL, "query %d: unknown kind %d", i, qq.kind);
+        const bool has_stats = qq.kind != CUBE_Q_HIST;
+        const bool has_hist = qq.kind != CUBE_Q_STATS;
+        if (has_hist) {
+            if (qq.nbins < 1 || qq.nbins > 32768)
+                return fail(CUBE_EINVAL, "query %d: batched histograms take 1..32768 bins", i);
+            if (qq.kind == CUBE_Q_HIST || qq.kind == CUBE_Q_FUSED) {
+                if ((rc = check_range(qq.lo, qq.hi, qq.nbins, &it.range)))
+                    return fail(rc, "query %d: %s", i, cube_last_error());
+            }
+            if (!qq.counts) return fail(CUBE_EINVAL, "query %d: counts is NULL", i);
+            if (qq.nbins > max_bins) max_bins = qq.nbins;
+        } else {
+            it.nbins = 1;
+        }
+        if (has_stats && !qq.out) return fail(CUBE_EINVAL, "query %d: out is NULL", i);
+        it.out = qq.out;
+        it.counts = (unsigned long long *)qq.counts;
+        collapse(box, &it.g);
+        // Segments of at most one tile; whole rows per tile when rows are short.
+        Geom &g = it.g;
+        long long seg = g.row_len < b->tile_voxels ? g.row_len : b->tile_voxels;
+        seg = (seg + 3) & ~3LL;
+        if (seg < 4) seg = 4;
+        g.seg_len = seg;
+        g.segs = box.n == 0 ? 1 : (g.row_len + seg - 1) / seg;
+        g.n_units = box.n == 0 ? 0 : g.ny * g.nz * g.segs;
+        long long upt = b->tile_voxels / seg;
+        if (upt < 1) upt = 1;
+        it.units_per_tile = upt;
+        const long long nt = g.n_units == 0 ? 1 : (g.n_units + upt - 1) / upt;
+        it.ntiles1 = (int32_t)nt;
+        it.ntiles2 = qq.kind == CUBE_Q_MINMAX ? (int32_t)nt : 0;
+        it.rec1 = (long long)n_recs;
+        n_recs += (size_t)nt * nw;
+        it.rec2 = (long long)n_recs;
+        n_recs += (size_t)it.ntiles2 * nw;
+        it.acc0 = (long long)n_acc;
+        n_acc += has_hist ? (size_t)qq.nbins : 0;
+        n_tiles += (size_t)(it.ntiles1 + it.ntiles2);
+        order[(size_t)i] = i;
+    }
+    if (n_tiles > (size_t)0x7fffffff) return fail(CUBE_EINVAL, "too many tiles");
+    int rc = ensure(b, (size_t)n, n_tiles, n_recs, n_acc);
+    if (rc) return rc;
+    drop_graph(b);
+    // Work list: phase-1 tiles, largest queries first, then phase-2 tiles in
+    // the same order.
+    std::vector<long long> sz((size_t)n);
+    for (int i = 0; i < n; ++i) sz[(size_t)i] = items[(size_t)i].ntiles1;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](long long x, long long y) { return sz[(size_t)x] > sz[(size_t)y]; });
+    // A launch still running on another stream reads the device work list:
+    // wait for it.  On the same stream, stream order protects the device
+    // buffers; the pinned staging must still have been read by the previous
+    // copy before it is rewritten.
+    if (b->have_work && b->last_stream != s) hipStreamSynchronize(b->last_stream);
+    if (b->staged) hipEventSynchronize(b->staged);
+    size_t k = 0;
+    for (int phase = 1; phase <= 2; ++phase)
+        for (long long i : order) {
+            const BatchItem &it = items[(size_t)i];
+            const int nt = phase == 1 ? it.ntiles1 : it.ntiles2;
+            for (int t = 0; t < nt; ++t) {
+                BatchTile &bt = b->h_tiles[k++];
+                bt.item = (int32_t)i;
+                bt.phase = phase;
+                bt.local = t;
+                bt.pad = 0;
+            }
+        }
+    memcpy(b->h_items, items.data(), (size_t)n * sizeof(BatchItem));
+    hipError_t e;
+    if (n > 0 &&
+        ((e = hipMemcpyAsync(b->d_items, b->h_items, (size_t)n * sizeof(BatchItem),
+                             hipMemcpyHostToDevice, s)) != hipSuccess ||
+         (e = hipMemcpyAsync(b->d_tiles, b->h_tiles, n_tiles * sizeof(BatchTile),
+                             hipMemcpyHostToDevice, s)) != hipSuccess))
+        return hip_fail(e, "work-list copy");
+    if (n > 0) {
+        if (!b->staged && (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "event");
+        if ((e = hipEventRecord(b->staged, s)) != hipSuccess) return hip_fail(e, "event record");
+    }
+    // Launch shape: one histogram copy layout for the batch, a grid of
+    // resident blocks.
+    int clog = 0;
+    while (clog < 4 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= 32 * 1024) ++clog;
+    b->lds = ((size_t)(max_bins + 2) << clog) * 4;
+    int bpc = 1;
+    if ((e = batch_occupancy(b->threads, b->lds, &bpc)) != hipSuccess)
+        return hip_fail(e, "batch occupancy");
+    if (bpc < 1) bpc = 1;
+    long long blocks = (long long)cu_count() * bpc;
+    if (blocks > (long long)n_tiles) blocks = (long long)n_tiles;
+    if (blocks < 1) blocks = 1;
+    b->blocks = (int)blocks;
+    BatchArgs &a = b->args;
+    a.items = b->d_items;
+    a.state = b->d_state;
+    a.tiles = b->d_tiles;
+    a.n_tiles = (int32_t)n_tiles;
+    a.copies_log2 = clog;
+    a.recs = b->d_recs;
+    a.acc = b->d_acc;
+    a.ctl = b->d_ctl;
+    a.accum_mode = CUBE_ACCUM_FP64MERGE;
+    a.spin_limit = 1u << 24;
+    b->have_work = n > 0;
+    if (!b->have_work) return CUBE_OK;
+    return launch_batch(b, s);
+}
+
+int cube_batch_relaunch(cube_batch_t *b, void *stream)
+{
+    if (!b) return fail(CUBE_EINVAL, "batch is NULL");
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (!b->have_work) return CUBE_OK;
+    return launch_batch(b, (hipStream_t)stream);
+}
+
+int cube_batch_graph_launch(cube_batch_t *b, void *stream)
+{
+    if (!b) return fail(CUBE_EINVAL, "batch is NULL");
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (!b->have_work) return CUBE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!b->graph_exec || b->graph_stream != s) {
+        drop_graph(b);
+        // Capture on a private stream (a legacy default stream cannot be
+        // captured), then replay the graph on the caller's stream.
+        hipStream_t cap;
+        if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "capture stream");
+        if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            hipStreamDestroy(cap);
+            return hip_fail(e, "begin capture");
+        }
+        BatchArgs a = b->args;
+        void *args[] = {&a};
+        e = hipLaunchKernel(reinterpret_cast<const void *>(&k_batch), dim3(b->blocks),
+                            dim3(b->threads), args, b->lds, cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &g);
+        hipStreamDestroy(cap);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+        }
+        hipGraphExec_t ge = nullptr;
+        if ((e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0)) != hipSuccess) {
+            hipGraphDestroy(g);
+            return hip_fail(e, "graph instantiate");
+        }
+        b->graph = g;
+        b->graph_exec = ge;
+        b->graph_stream = s;
+    }
+    if ((e = hipGraphLaunch(b->graph_exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    b->last_stream = s;
+    return CUBE_OK;
+}
+
+int cube_batch_check(cube_batch_t *b)
+{
+    if (!b) return fail(CUBE_EINVAL, "batch is NULL");
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (!b->d_ctl) return CUBE_OK;
+    unsigned int ctl[4] = {0, 0, 0, 0};
+    hipError_t e;
+    if (b->have_work && (e = hipStreamSynchronize(b->last_stream)) != hipSuccess)
+        return hip_fail(e, "batch synchronize");
+    if ((e = hipMemcpy(ctl, b->d_ctl, sizeof ctl, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "batch status copy");
+    if (ctl[2]) return fail(CUBE_EDEVICE, "a batched two-pass query timed out waiting for its "
+                                          "range; its histogram is incomplete");
+    return CUBE_OK;
+}
+
+int cube_batch_run(const cube_query_t *q, int32_t n)
+{
+    cube_batch_t *b = nullptr;
+    int rc = cube_batch_create(&b);
+    if (rc) return rc;
+    rc = cube_batch_enqueue(b, q, n, nullptr);
+    if (!rc) rc = cube_batch_check(b);
+    cube_batch_destroy(b);
+    return rc;
+}
+
+}  // extern "C"

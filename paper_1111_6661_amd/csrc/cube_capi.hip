@@ -14,12 +14,7 @@
 
 #include "cube_internal.h"
 
-using cube::Geom;
-using cube::HistRange;
-using cube::PassArgs;
-using cube::WaveRec;
-
-namespace {
+namespace cube {
 
 thread_local std::string g_err;
 
@@ -40,12 +35,14 @@ int hip_fail(hipError_t e, const char *what)
 }
 
 std::atomic<int> g_accum{CUBE_ACCUM_FP64MERGE};
-std::atomic<int> g_threads{0}, g_blocks{0}, g_copies{0};
+
+int accum_mode() { return g_accum.load(); }
+std::atomic<int> g_threads{0}, g_blocks{0}, g_copies{0}, g_unroll{0};
 
 constexpr int MAX_BLOCKS = 4096;
 constexpr int MAX_WAVES_PER_BLOCK = 16;
 constexpr size_t REC_CAP = (size_t)MAX_BLOCKS * MAX_WAVES_PER_BLOCK;
-constexpr size_t LDS_BUDGET = 80 * 1024;   // two histogram blocks per CU
+constexpr size_t LDS_BUDGET = 132 * 1024;  // one 1024-thread histogram block per CU
 
 // One workspace per (device, stream): partial records, the ticket, the
 // histogram accumulators (kept at zero between launches by the kernel) and
@@ -142,11 +139,6 @@ int cu_count()
 }
 
 // ---------------------------------------------------------------- validation
-struct Box {
-    const float *ptr;
-    int64_t nx, ny, nz, sy, sz;
-    uint64_t n;
-};
 
 int check_box(const float *ptr, const int64_t *dims, Box *b)
 {
@@ -239,11 +231,6 @@ int check_range(float lo, float hi, int32_t nbins, HistRange *r)
 }
 
 // ------------------------------------------------------------------ planning
-struct Plan {
-    Geom g;
-    int threads, blocks, copies_log2, hist;
-    size_t lds;
-};
 
 void collapse(const Box &b, Geom *g)
 {
@@ -276,15 +263,17 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
 {
     collapse(b, &p->g);
     int threads = g_threads.load();
-    if (threads != 256 && threads != 512 && threads != 1024) threads = hist_kind_req ? 512 : 256;
+    if (threads != 256 && threads != 512 && threads != 1024) threads = hist_kind_req ? 1024 : 256;
     p->threads = threads;
-    p->hist = cube::HIST_NONE;
+    int unroll = g_unroll.load();
+    p->unroll = (unroll == 2 || unroll == 4 || unroll == 8) ? unroll : 4;
+    p->hist = HIST_NONE;
     p->copies_log2 = 0;
     if (hist_kind_req) {
         if (nbins > 32768) {
-            p->hist = cube::HIST_GLOBAL;
+            p->hist = HIST_GLOBAL;
         } else {
-            p->hist = cube::HIST_LDS;
+            p->hist = HIST_LDS;
             int c = g_copies.load();
             int clog = 0;
             if (c > 0) {
@@ -297,9 +286,13 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
             p->copies_log2 = clog;
         }
     }
-    p->lds = cube::pass_lds_bytes(stats, p->hist, nbins, p->copies_log2, threads);
-    const int bpc = cube::pass_blocks_per_cu(stats, p->hist, threads, p->lds);
-    const long long cap = (long long)cu_count() * bpc;
+    p->lds = pass_lds_bytes(stats, p->hist, nbins, p->copies_log2, threads);
+    const int bpc = pass_blocks_per_cu(stats, p->hist, threads, p->lds, p->unroll);
+    // At least four blocks per CU over the launch: with one resident
+    // histogram block per CU, four waves of blocks measured faster than one
+    // persistent wave on large boxes (shorter per-block ranges, overlapped
+    // tails).
+    const long long cap = (long long)cu_count() * (bpc < 4 ? 4 : bpc);
     const long long per_block_min = (long long)threads * 16 * 2;  // two main-loop steps
     long long blocks = g_blocks.load();
     if (blocks <= 0) {
@@ -346,7 +339,8 @@ __global__ void k_write_empty(cube_stats_t *out, unsigned long long *counts, int
 
 int launch(const PassArgs &a, const Plan &p, bool stats, hipStream_t s)
 {
-    hipError_t e = cube::launch_pass(a, stats, p.hist, p.threads, p.blocks, p.lds, s);
+    hipError_t e =
+        launch_pass(a, stats, p.hist, p.threads, p.blocks, p.lds, p.unroll, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return CUBE_OK;
 }
@@ -476,7 +470,9 @@ int run_async_entry(Op op, const float *ptr, const int64_t *dims, float lo, floa
                      (hipStream_t)stream, w);
 }
 
-}  // namespace
+}  // namespace cube
+
+using namespace cube;
 
 extern "C" {
 
@@ -549,16 +545,19 @@ int cube_set_accum_mode(int32_t mode)
     return g_accum.exchange(mode);
 }
 
-int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies)
+int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll)
 {
     if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
         return fail(CUBE_EINVAL, "threads must be 0, 256, 512 or 1024");
     if (blocks < 0 || blocks > MAX_BLOCKS) return fail(CUBE_EINVAL, "blocks outside [0, 4096]");
     if (hist_copies < 0 || hist_copies > 32 || (hist_copies & (hist_copies - 1)))
         return fail(CUBE_EINVAL, "hist_copies must be 0 or a power of two <= 32");
+    if (unroll != 0 && unroll != 2 && unroll != 4 && unroll != 8)
+        return fail(CUBE_EINVAL, "unroll must be 0, 2, 4 or 8");
     g_threads = threads;
     g_blocks = blocks;
     g_copies = hist_copies;
+    g_unroll = unroll;
     return CUBE_OK;
 }
 

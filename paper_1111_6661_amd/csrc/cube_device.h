@@ -1,0 +1,526 @@
+// cube_device.h -- device code shared by the single-box and the batched
+// kernels of the cube statistics library: the per-voxel step, the scan of a
+// box's work units, the wavefront record (local stage), the LDS histogram
+// flush and the FP64 merge of records (global stage).
+//
+// Per voxel:
+//   * blank test (x != x), counted with a wavefront ballot on the scalar unit;
+//   * min / max of the quieted value (v_min3/v_max3 order -0 before +0 and
+//     skip quiet NaNs; a signalling NaN is quieted first);
+//   * moments d = x - K and d^2 about a per-wavefront pivot K (the first
+//     valid voxel the wavefront meets), summed in FP32 over a short chunk and
+//     folded into a TwoSum-compensated lane accumulator (Knuth's TwoSum);
+//   * the histogram bin min(nbins-1, floor((x - lo) * scale)) in FP32 (two
+//     rounded operations, then v_cvt_flr_i32_f32), counted in LDS
+//     sub-histograms interleaved per lane; blank and out-of-range voxels go
+//     to a dummy slot and are counted with ballots instead.
+#pragma once
+
+#include <math.h>
+
+#include "cube_internal.h"
+
+namespace cube {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int MAX_WAVES = 16;   // 1024 threads per block at most
+
+__device__ __forceinline__ int cvt_flr_i32(float u)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(u));
+    return r;
+}
+
+__device__ __forceinline__ float qnan() { return __int_as_float(0x7fc00000); }
+
+// s + c += x with the rounding error of s + x kept in c (TwoSum).
+__device__ __forceinline__ void two_sum_acc(float &s, float &c, float x)
+{
+    const float t = s + x;
+    const float bp = t - s;
+    const float e = (s - (t - bp)) + (x - bp);
+    s = t;
+    c += e;
+}
+
+// (ah, al) += (bh, bl), double-float addition.
+__device__ __forceinline__ void df_add(float &ah, float &al, float bh, float bl)
+{
+    const float s = ah + bh;
+    const float bp = s - ah;
+    float e = (ah - (s - bp)) + (bh - bp);
+    e += al + bl;
+    ah = s + e;
+    al = e - (ah - s);
+}
+
+struct Lane {
+    float mn, mx, s1, c1, s2, c2;
+};
+
+struct Wave {  // wavefront-uniform
+    float K;
+    int has_k;
+    unsigned long long slots, nan, below, above;  // lane-voxel slots seen, and ballots
+};
+
+// The histogram as one voxel sees it.  LDS layout: slot b of copy c is the
+// word b * C + c (C = 1 << copies_log2 copies, interleaved so that lanes of
+// one wavefront hitting the same bin hit different banks).  Slots 0..nbins-1
+// are the bins; slot nbins collects the x == hi-side rounding case
+// floor(u) == nbins and is added to bin nbins-1 at the flush (this is the
+// min(nbins-1, .) of the bin rule); slot nbins+1 collects blank and
+// out-of-range voxels, which are counted with ballots instead.
+struct Hist {
+    float lo, hi, scale;
+    int nbins, shift, lane_off, dummy;
+    unsigned int *lds;
+    unsigned long long *global;
+};
+
+// v ? with the lanes of `m` replaced: m[lane] ? w : v (one v_cndmask_b32 reading a
+// ballot mask, so the mask a ballot already produced is not recomputed).
+__device__ __forceinline__ float zero_where(float v, unsigned long long m)
+{
+    float r;
+    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(v), "s"(m));
+    return r;
+}
+__device__ __forceinline__ int replace_where(int v, int w, unsigned long long m)
+{
+    int r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(v), "v"(w), "s"(m));
+    return r;
+}
+
+template <bool STATS, int HIST, int ACC, int NV>
+__device__ __forceinline__ void process(const float (&x)[NV], Lane &L, Wave &W,
+                                        const Hist &H)
+{
+    if (STATS && ACC != CUBE_ACCUM_NAIVE32 && !W.has_k) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(x[j] == x[j]);
+            if (m) {
+                const int l = __builtin_ctzll(m);
+                W.K = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[j]), l));
+                W.has_k = 1;
+                break;
+            }
+        }
+    }
+    // Ballot counts of this step in 32-bit scalars (at most 64 * NV each).
+    unsigned int cnan = 0, cbelow = 0, cabove = 0;
+    float t1 = 0.f, t2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const float v = x[j];
+        const unsigned long long mnan = __builtin_amdgcn_ballot_w64(v != v);
+        cnan += __popcll(mnan);
+        if (STATS) {
+            const float q = __builtin_canonicalizef(v);
+            L.mn = fminf(L.mn, q);
+            L.mx = fmaxf(L.mx, q);
+            if (ACC == CUBE_ACCUM_NAIVE32) {
+                const float d = zero_where(v, mnan);
+                L.s1 += d;
+                L.s2 = __fmaf_rn(d, d, L.s2);
+            } else {
+                const float d = zero_where(__fsub_rn(v, W.K), mnan);
+                t1 += d;
+                t2 = __fmaf_rn(d, d, t2);
+            }
+        }
+        if (HIST != HIST_NONE) {
+            const unsigned long long mbelow = __builtin_amdgcn_ballot_w64(v < H.lo);
+            const unsigned long long mabove = __builtin_amdgcn_ballot_w64(v > H.hi);
+            cbelow += __popcll(mbelow);
+            cabove += __popcll(mabove);
+            const unsigned long long mout = mnan | mbelow | mabove;
+            const float u = __fmul_rn(__fsub_rn(v, H.lo), H.scale);
+            if (HIST == HIST_LDS) {
+                const int b = replace_where(cvt_flr_i32(u), H.dummy, mout);
+                atomicAdd((unsigned int *)((char *)H.lds + ((b << H.shift) + H.lane_off)), 1u);
+            } else {
+                const int b = min(cvt_flr_i32(u), H.nbins - 1);
+                if (!((mout >> (threadIdx.x & 63)) & 1ull)) atomicAdd(&H.global[b], 1ull);
+            }
+        }
+    }
+    // Keep the step counts 32-bit (the compiler would otherwise widen every
+    // per-voxel add to 64 bits).
+    asm("" : "+s"(cnan), "+s"(cbelow), "+s"(cabove));
+    W.slots += 64u * NV;
+    W.nan += cnan;
+    W.below += cbelow;
+    W.above += cabove;
+    if (STATS && ACC != CUBE_ACCUM_NAIVE32) {
+        two_sum_acc(L.s1, L.c1, t1);
+        two_sum_acc(L.s2, L.c2, t2);
+    }
+}
+
+// Pairwise merge of (n, mean, m2) summaries (Chan, Golub & LeVeque).
+template <typename T>
+__device__ __forceinline__ void chan_merge(double &n, T &mean, T &m2, double nb, T mb, T m2b)
+{
+    if (nb == 0.0) return;
+    if (n == 0.0) {
+        n = nb;
+        mean = mb;
+        m2 = m2b;
+        return;
+    }
+    const double nt = n + nb;
+    const T d = mb - mean;
+    mean = mean + d * (T)(nb / nt);
+    m2 = m2 + m2b + d * d * (T)(n * nb / nt);
+    n = nt;
+}
+
+template <typename T>
+struct Summary {
+    double n;
+    T mean, m2;
+    float mn, mx;
+    unsigned long long nv, below, above;
+};
+
+template <typename T>
+__device__ __forceinline__ void summary_merge(Summary<T> &a, const Summary<T> &b)
+{
+    chan_merge<T>(a.n, a.mean, a.m2, b.n, b.mean, b.m2);
+    a.mn = fminf(a.mn, b.mn);
+    a.mx = fmaxf(a.mx, b.mx);
+    a.nv += b.nv;
+    a.below += b.below;
+    a.above += b.above;
+}
+
+template <typename T>
+__device__ __forceinline__ Summary<T> shfl_xor_summary(const Summary<T> &s, int off)
+{
+    Summary<T> o;
+    o.n = __shfl_xor(s.n, off);
+    o.mean = __shfl_xor(s.mean, off);
+    o.m2 = __shfl_xor(s.m2, off);
+    o.mn = __shfl_xor(s.mn, off);
+    o.mx = __shfl_xor(s.mx, off);
+    o.nv = __shfl_xor(s.nv, off);
+    o.below = __shfl_xor(s.below, off);
+    o.above = __shfl_xor(s.above, off);
+    return o;
+}
+
+// The global stage: every thread folds a fixed slice of the wavefront
+// records in order, then a fixed xor-tree inside each wavefront, then the
+// wavefront summaries in order.  Deterministic for a given grid.
+template <typename T, int ACC>
+__device__ Summary<T> merge_records(const WaveRec *recs, int n_recs)
+{
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int r0 = (int)(((long long)n_recs * tid) / B);
+    const int r1 = (int)(((long long)n_recs * (tid + 1)) / B);
+    Summary<T> s = {0.0, (T)0, (T)0, INFINITY, -INFINITY, 0ull, 0ull, 0ull};
+    for (int r = r0; r < r1; ++r) {
+        const WaveRec w = recs[r];
+        s.below += w.below;
+        s.above += w.above;
+        if (w.n_valid == 0) continue;
+        s.nv += w.n_valid;
+        s.mn = fminf(s.mn, w.mn);
+        s.mx = fmaxf(s.mx, w.mx);
+        const double nb = (double)w.n_valid;
+        T mb, m2b;
+        if (ACC == CUBE_ACCUM_NAIVE32) {
+            const T S1 = (T)w.s1h, S2 = (T)w.s2h, n = (T)nb;
+            mb = S1 / n;
+            m2b = S2 - S1 * S1 / n;
+        } else {
+            const T S1 = (T)w.s1h + (T)w.s1l;
+            const T S2 = (T)w.s2h + (T)w.s2l;
+            mb = (T)w.K + S1 / (T)nb;
+            m2b = S2 - S1 * S1 / (T)nb;
+        }
+        if (m2b < (T)0) m2b = (T)0;
+        chan_merge<T>(s.n, s.mean, s.m2, nb, mb, m2b);
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+        Summary<T> o = shfl_xor_summary(s, off);
+        // Fixed pairing: the lower lane of each pair is the left operand.
+        if ((threadIdx.x & off) == 0) {
+            summary_merge(s, o);
+        } else {
+            summary_merge(o, s);
+            s = o;
+        }
+    }
+    __shared__ Summary<T> ws[MAX_WAVES];
+    const int lane = tid & 63, wid = tid >> 6, nw = B >> 6;
+    if (lane == 0) ws[wid] = s;
+    __syncthreads();
+    Summary<T> t = ws[0];
+    for (int w = 1; w < nw; ++w) summary_merge(t, ws[w]);
+    return t;
+}
+
+// One tile: U float4 loads per lane, lane stride B; uniform base + fixed
+// per-lane 32-bit byte offsets, so the loads use scalar-base addressing.
+template <int U>
+__device__ __forceinline__ void load_tile(f4 (&v)[U], const f4 *q4, long long off, int B, int tid)
+{
+    const char *base = (const char *)(q4 + off);
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+        v[k] = __builtin_nontemporal_load((const f4 *)(base + (unsigned int)((k * B + tid) * 16)));
+}
+
+template <bool STATS, int HIST, int ACC, int U>
+__device__ __forceinline__ void process_tile(const f4 (&v)[U], Lane &L, Wave &W, const Hist &H)
+{
+    float xv[4 * U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        xv[4 * k + 0] = v[k].x;
+        xv[4 * k + 1] = v[k].y;
+        xv[4 * k + 2] = v[k].z;
+        xv[4 * k + 3] = v[k].w;
+    }
+    process<STATS, HIST, ACC, 4 * U>(xv, L, W, H);
+}
+
+// Histogram context of a pass over the range r (an invalid range -- lo = +inf,
+// hi = -inf -- sends every voxel out of range).  Returns whether it is valid.
+__device__ __forceinline__ bool hist_setup(Hist &H, const HistRange &r, int nbins,
+                                           int copies_log2, unsigned int *lds,
+                                           unsigned long long *acc)
+{
+    const int lane = threadIdx.x & 63;
+    H.nbins = nbins;
+    H.shift = copies_log2 + 2;
+    H.lane_off = (lane & ((1 << copies_log2) - 1)) * 4;
+    H.lds = lds;
+    H.global = acc;
+    H.dummy = nbins + 1;
+    const bool on = (r.ok == 1);
+    H.lo = on ? r.lo : INFINITY;
+    H.hi = on ? r.hi : -INFINITY;
+    H.scale = on ? r.scale : 0.f;
+    return on;
+}
+
+// Zero the LDS sub-histograms (nbins + 2 slots per copy); ends with a barrier.
+__device__ __forceinline__ void lds_zero(unsigned int *lds, int nbins, int copies_log2)
+{
+    const int words = (nbins + 2) << copies_log2;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
+    __syncthreads();
+}
+
+// Scan the work units [u0, u1) of a box (segments of rows, see Geom).
+template <bool STATS, int HIST, int ACC, int U>
+__device__ __forceinline__ void scan_units(const Geom &g, long long u0, long long u1, Lane &L,
+                                           Wave &W, const Hist &H)
+{
+    if (u0 >= u1) return;
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    long long row = u0 / g.segs;
+    long long s = u0 - row * g.segs;
+    long long y = row % g.ny;
+    long long z = row / g.ny;
+    for (long long u = u0; u < u1; ++u) {
+        const float *q = g.ptr + y * g.sy + z * g.sz + s * g.seg_len;
+        const long long c0 = s * g.seg_len;
+        const long long len = min(g.seg_len, g.row_len - c0);
+        const long long mis = (long long)((16 - ((uintptr_t)q & 15)) & 15) >> 2;
+        const long long h = min(len, mis);
+        const long long n4 = (len - h) >> 2;
+        const long long t = len - h - 4 * n4;
+        if (wid == 0 && h + t > 0) {
+            // Head and tail voxels: lanes [0, h) and [h, h + t).
+            long long idx = lane < h ? lane : h + 4 * n4 + (lane - h);
+            const bool have = lane < h + t;
+            idx = have ? idx : 0;
+            float xv[1];
+            const float v = q[idx];
+            xv[0] = have ? v : qnan();
+            process<STATS, HIST, ACC, 1>(xv, L, W, H);
+        }
+        const f4 *q4 = (const f4 *)(q + h);
+        // Full tiles, software-pipelined: the next tile's loads are in
+        // flight while the current tile is processed.
+        const long long T = (long long)B * U;
+        const long long ntiles = n4 / T;
+        if (ntiles > 0) {
+            f4 va[U], vb[U];
+            load_tile<U>(va, q4, 0, B, tid);
+            long long k = 0;
+            while (true) {
+                if (k + 1 < ntiles) load_tile<U>(vb, q4, (k + 1) * T, B, tid);
+                process_tile<STATS, HIST, ACC, U>(va, L, W, H);
+                if (++k == ntiles) break;
+                if (k + 1 < ntiles) load_tile<U>(va, q4, (k + 1) * T, B, tid);
+                process_tile<STATS, HIST, ACC, U>(vb, L, W, H);
+                if (++k == ntiles) break;
+            }
+        }
+        for (long long i0 = ntiles * T; i0 < n4; i0 += B) {
+            const long long i = i0 + tid;
+            const bool have = i < n4;
+            const f4 v = __builtin_nontemporal_load(q4 + (have ? i : n4 - 1));
+            float xv[4];
+            xv[0] = have ? v.x : qnan();
+            xv[1] = have ? v.y : qnan();
+            xv[2] = have ? v.z : qnan();
+            xv[3] = have ? v.w : qnan();
+            process<STATS, HIST, ACC, 4>(xv, L, W, H);
+        }
+        if (++s == g.segs) {
+            s = 0;
+            if (++y == g.ny) {
+                y = 0;
+                ++z;
+            }
+        }
+    }
+}
+
+// Local stage: reduce the lanes of the calling wavefront into one record
+// (written by lane 0).
+template <bool STATS, int ACC>
+__device__ __forceinline__ void write_wave_record(const Lane &L, const Wave &W, WaveRec *dst)
+{
+    float mn = L.mn, mx = L.mx, s1h = L.s1, s1l = L.c1, s2h = L.s2, s2l = L.c2;
+    if (STATS) {
+        for (int off = 32; off > 0; off >>= 1) {
+            mn = fminf(mn, __shfl_xor(mn, off));
+            mx = fmaxf(mx, __shfl_xor(mx, off));
+            const float o1h = __shfl_xor(s1h, off), o1l = __shfl_xor(s1l, off);
+            const float o2h = __shfl_xor(s2h, off), o2l = __shfl_xor(s2l, off);
+            if (ACC == CUBE_ACCUM_NAIVE32) {
+                s1h += o1h;
+                s2h += o2h;
+            } else {
+                df_add(s1h, s1l, o1h, o1l);
+                df_add(s2h, s2l, o2h, o2l);
+            }
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        WaveRec r;
+        r.K = W.K;
+        r.s1h = s1h;
+        r.s1l = s1l;
+        r.s2h = s2h;
+        r.s2l = s2l;
+        r.mn = mn;
+        r.mx = mx;
+        r.pad = 0.f;
+        r.n_valid = W.slots - W.nan;
+        r.below = W.below;
+        r.above = W.above;
+        r.pad2 = 0ull;
+        *dst = r;
+    }
+}
+
+// Add the block's LDS sub-histograms into the global accumulators (one
+// atomic per non-empty bin).  Starts with a barrier.
+__device__ __forceinline__ void hist_flush(const unsigned int *lds, int nbins, int copies_log2,
+                                           unsigned long long *acc)
+{
+    __syncthreads();
+    const int C = 1 << copies_log2;
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+        unsigned int sum = 0;
+        for (int c = 0; c < C; ++c) sum += lds[(b << copies_log2) + c];
+        if (b == nbins - 1)  // floor(u) == nbins belongs to the last bin
+            for (int c = 0; c < C; ++c) sum += lds[(nbins << copies_log2) + c];
+        if (sum) atomicAdd(&acc[b], (unsigned long long)sum);
+    }
+}
+
+// The global stage of a stats pass: merge `n_recs` records (all threads of
+// the block call it), then thread 0 writes the result and, when `range_out`
+// is given, the [min, max] histogram range with its FP32 scale.  Returns the
+// total valid / below / above counts to every thread.
+template <int ACC>
+__device__ void finish_stats(const WaveRec *recs, int n_recs, int accum_mode,
+                             unsigned long long n_total, cube_stats_t *out,
+                             HistRange *range_out, int nbins, unsigned long long &nv,
+                             unsigned long long &below, unsigned long long &above)
+{
+    float fmn, fmx;
+    double mean, m2;
+    if (accum_mode == CUBE_ACCUM_FP64MERGE) {
+        const Summary<double> S = merge_records<double, ACC>(recs, n_recs);
+        nv = S.nv; below = S.below; above = S.above;
+        fmn = S.mn; fmx = S.mx; mean = S.mean; m2 = S.m2;
+    } else {
+        const Summary<float> S = merge_records<float, ACC>(recs, n_recs);
+        nv = S.nv; below = S.below; above = S.above;
+        fmn = S.mn; fmx = S.mx; mean = (double)S.mean; m2 = (double)S.m2;
+    }
+    if (threadIdx.x != 0) return;
+    cube_stats_t o;
+    o.n_total = n_total;
+    o.n_valid = nv;
+    o.n_nan = n_total - nv;
+    o.flags = 0u;
+    o.reserved = 0u;
+    if (nv == 0) {
+        o.min = o.max = qnan();
+        o.mean = o.m2 = o.std = (double)qnan();
+        o.flags |= CUBE_NO_VALID;
+    } else {
+        o.min = fmn;
+        o.max = fmx;
+        o.mean = mean;
+        o.m2 = m2 < 0.0 ? 0.0 : m2;
+        o.std = accum_mode == CUBE_ACCUM_FP64MERGE ? sqrt(o.m2 / (double)nv)
+                                                   : (double)sqrtf((float)o.m2 / (float)nv);
+    }
+    if (range_out) {
+        HistRange r = {qnan(), qnan(), 0.f, 2};
+        if (nv != 0) {
+            r.ok = 0;
+            if (isfinite(fmn) && isfinite(fmx)) {
+                const float w = __fsub_rn(fmx, fmn);
+                if (isfinite(w)) {
+                    const float sc = w == 0.f ? 0.f : __fdiv_rn((float)nbins, w);
+                    if (isfinite(sc)) {
+                        r.lo = fmn;
+                        r.hi = fmx;
+                        r.scale = sc;
+                        r.ok = 1;
+                    }
+                }
+            }
+            if (r.ok == 0) o.flags |= CUBE_HIST_BAD_RANGE;
+        }
+        *range_out = r;
+    }
+    *out = o;
+}
+
+// Copy the global accumulators to the caller's counts and return them to
+// zero; thread 0 writes below / above / NaN.
+__device__ __forceinline__ void finish_hist(unsigned long long *acc, unsigned long long *counts,
+                                            int nbins, bool on, unsigned long long below,
+                                            unsigned long long above, unsigned long long n_nan)
+{
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+        counts[b] = acc[b];
+        acc[b] = 0ull;
+    }
+    if (threadIdx.x == 0) {
+        counts[nbins] = on ? below : 0ull;
+        counts[nbins + 1] = on ? above : 0ull;
+        counts[nbins + 2] = n_nan;
+    }
+}
+
+}  // namespace cube

@@ -56,13 +56,41 @@ struct PassArgs {
 
 // Kernel launchers (cube_kernels.hip).  `stats`: compute the statistics;
 // `hist`: HIST_NONE / HIST_LDS / HIST_GLOBAL.  Returns the launch error.
+// `unroll`: float4 loads per lane per pipelined tile (2, 4 or 8).
 hipError_t launch_pass(const PassArgs &a, bool stats, int hist, int threads,
-                       int blocks, size_t lds_bytes, hipStream_t s);
+                       int blocks, size_t lds_bytes, int unroll, hipStream_t s);
 
 // Dynamic LDS bytes a pass needs.
 size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int threads);
 
 // Occupancy of one pass configuration: resident blocks per CU.
-int pass_blocks_per_cu(bool stats, int hist, int threads, size_t lds_bytes);
+int pass_blocks_per_cu(bool stats, int hist, int threads, size_t lds_bytes, int unroll);
+
+// ------------------------------------------------ host helpers (cube_capi.hip)
+// A validated box: extents, pitches (defaults resolved) and voxel count.
+struct Box {
+    const float *ptr;
+    int64_t nx, ny, nz, sy, sz;
+    uint64_t n;
+};
+
+struct Plan {
+    Geom g;
+    int threads, blocks, copies_log2, hist, unroll;
+    size_t lds;
+};
+
+// Set the calling thread's error text and return `code`.
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+// Host-only checks of a box (no HIP call) and the checks that need HIP.
+int check_box(const float *ptr, const int64_t *dims, Box *b);
+int check_box_device(const Box *b);
+// Validate a histogram range and form its FP32 scale.
+int check_range(float lo, float hi, int32_t nbins, HistRange *r);
+// Merge contiguous axes of a box into rows (segments not yet set).
+void collapse(const Box &b, Geom *g);
+int cu_count();
+int accum_mode();
 
 }  // namespace cube

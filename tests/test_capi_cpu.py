@@ -90,7 +90,7 @@ def test_mode_and_launch_setters_validate():
     assert _code(cs.cube_set_launch, 256, 0, 3)[0] == cs.CUBE_EINVAL
     prev = cs.cube_set_accum_mode(cs.CUBE_ACCUM_KAHAN32)
     assert cs.cube_set_accum_mode(prev) == cs.CUBE_ACCUM_KAHAN32
-    cs.cube_set_launch(0, 0, 0)
+    cs.cube_set_launch(0, 0, 0, 0)
 
 
 def test_binding_has_no_cpu_fallback():

@@ -1,0 +1,144 @@
+"""The batched persistent launch (GPU) against the oracle and against each
+query run alone."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import assert_counts_match, assert_stats_match
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import paper_1111_6661_amd as cs
+    assert torch.cuda.is_available()
+    cs.load()
+    return cs
+
+
+class Outputs:
+    """Device output buffers for a list of queries."""
+
+    def __init__(self, n, nbins_max):
+        self.out = torch.zeros((n, 64), dtype=torch.uint8, device="cuda")
+        self.cnt = torch.zeros((n, nbins_max + 3), dtype=torch.int64, device="cuda")
+
+    def stats(self, cs, i):
+        return cs.Stats.from_bytes(self.out[i].cpu().numpy().tobytes())
+
+    def counts(self, i, nbins):
+        return self.cnt[i, :nbins + 3].cpu().numpy().view(np.uint64)
+
+
+def make_items(seed=5, n=12):
+    import synth
+    rng = np.random.default_rng(seed)
+    items = []
+    for k in range(n):
+        nx, ny, nz = (int(rng.integers(3, 200)), int(rng.integers(1, 60)), int(rng.integers(1, 40)))
+        r = synth.WORKLOADS["tiny"].scaled(nx, ny, nz)
+        t = synth.cube_tensor(r, 1000 + k, device="cuda")
+        items.append(t)
+    return items
+
+
+def queries_for(cs, items, outs, kinds, nbins_list):
+    qs = []
+    for i, t in enumerate(items):
+        ptr, d = cs.box_of(t)
+        kind = kinds[i % len(kinds)]
+        nb = nbins_list[i % len(nbins_list)]
+        lo, hi = -2.5, 20.0
+        qs.append(cs.make_query(ptr, d, kind, nb, lo, hi, outs.out[i].data_ptr(),
+                                outs.cnt[i].data_ptr()))
+    return qs
+
+
+def check_query(cs, outs, i, t, kind, nb):
+    host = t.cpu().numpy()
+    ref = oracle.stats(host)
+    if kind != cs.CUBE_Q_HIST:
+        assert_stats_match(outs.stats(cs, i), ref, f"item {i}")
+    if kind in (cs.CUBE_Q_HIST, cs.CUBE_Q_FUSED):
+        assert_counts_match(outs.counts(i, nb), oracle.hist(host, -2.5, 20.0, nb), f"item {i}")
+    if kind == cs.CUBE_Q_MINMAX:
+        assert_counts_match(outs.counts(i, nb), oracle.hist(host, ref.min, ref.max, nb),
+                            f"item {i} minmax")
+
+
+@pytest.mark.parametrize("tile", [4096, 1 << 16, 1 << 20])
+def test_mixed_batch_matches_oracle(cs, tile):
+    items = make_items()
+    kinds = [cs.CUBE_Q_STATS, cs.CUBE_Q_HIST, cs.CUBE_Q_FUSED, cs.CUBE_Q_MINMAX]
+    nbins_list = [64, 512, 1000, 7]
+    outs = Outputs(len(items), 1000)
+    qs = queries_for(cs, items, outs, kinds, nbins_list)
+    b = cs.Batch(tile_voxels=tile)
+    b.enqueue(qs)
+    b.check()
+    for i, t in enumerate(items):
+        check_query(cs, outs, i, t, kinds[i % 4], nbins_list[i % 4])
+    # relaunch and graph replay give the same bits
+    ref_out, ref_cnt = outs.out.clone(), outs.cnt.clone()
+    for launch in (b.relaunch, b.graph_launch, b.graph_launch, b.graph_launch):
+        outs.out.zero_()
+        outs.cnt.zero_()
+        torch.cuda.synchronize()
+        launch()
+        b.check()
+        assert torch.equal(outs.out, ref_out) and torch.equal(outs.cnt, ref_cnt)
+    b.close()
+
+
+def test_alone_equals_in_mix(cs):
+    items = make_items(seed=9, n=10)
+    kinds = [cs.CUBE_Q_MINMAX, cs.CUBE_Q_FUSED, cs.CUBE_Q_STATS]
+    nbins_list = [512, 256, 1]
+    mix = Outputs(len(items), 512)
+    b = cs.Batch(tile_voxels=1 << 14)
+    b.enqueue(queries_for(cs, items, mix, kinds, nbins_list))
+    b.check()
+    for i, t in enumerate(items):
+        alone = Outputs(1, 512)
+        q = queries_for(cs, [t], alone, [kinds[i % 3]], [nbins_list[i % 3]])
+        b2 = cs.Batch(tile_voxels=1 << 14)
+        b2.enqueue(q)
+        b2.check()
+        assert torch.equal(alone.out[0], mix.out[i]), f"item {i} stats differ alone vs mix"
+        assert torch.equal(alone.cnt[0], mix.cnt[i]), f"item {i} counts differ alone vs mix"
+        b2.close()
+    b.close()
+
+
+def test_batch_of_workload_items(cs):
+    """The 64-item workload shape (uneven sizes), two-pass 512 bins each."""
+    import synth
+    recs = synth.batch_item_recipes()[:16]
+    items = [synth.cube_tensor(r, 77 + i, device="cuda") for i, r in enumerate(recs)]
+    outs = Outputs(len(items), 512)
+    qs = queries_for(cs, items, outs, [cs.CUBE_Q_MINMAX], [512])
+    cs.cube_batch_run(qs)
+    for i, t in enumerate(items):
+        check_query(cs, outs, i, t, cs.CUBE_Q_MINMAX, 512)
+
+
+def test_batch_validation(cs):
+    t = torch.zeros(100, device="cuda")
+    ptr, d = cs.box_of(t)
+    out = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    bad = [cs.make_query(ptr, d, 9, 8, 0, 1, out.data_ptr(), out.data_ptr()),
+           cs.make_query(ptr, d, cs.CUBE_Q_HIST, 0, 0, 1, 0, out.data_ptr()),
+           cs.make_query(ptr, d, cs.CUBE_Q_HIST, 8, 2, 1, 0, out.data_ptr()),
+           cs.make_query(ptr, d, cs.CUBE_Q_STATS, 8, 0, 1, 0, 0),
+           cs.make_query(ptr, [1 << 30, 1, 1, 0, 0], cs.CUBE_Q_STATS, 0, 0, 0, out.data_ptr(), 0)]
+    for q in bad:
+        with pytest.raises(cs.CubeError):
+            cs.cube_batch_run([q])
+    # an empty box and an empty batch are fine
+    cs.cube_batch_run([])
+    e = cs.make_query(ptr, [0, 4, 4, 0, 0], cs.CUBE_Q_STATS, 0, 0, 0, out.data_ptr(), 0)
+    cs.cube_batch_run([e])
+    st = cs.Stats.from_bytes(out.cpu().numpy().tobytes())
+    assert st.n_total == 0 and st.flags & cs.CUBE_NO_VALID

@@ -23,7 +23,7 @@ def cs():
     import paper_1111_6661_amd as cs
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     cs.load()
-    cs.cube_set_launch(0, 0, 0)
+    cs.cube_set_launch(0, 0, 0, 0)
     cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
     return cs
 
@@ -179,20 +179,20 @@ def test_large_bin_counts(cs, tiny, nbins):
     assert_stats_match(st, ref, f"{nbins} bins")
 
 
-@pytest.mark.parametrize("threads,blocks,copies", [
-    (256, 0, 0), (512, 0, 1), (1024, 0, 32), (256, 1, 4), (512, 7, 2), (1024, 300, 8),
-    (256, 4096, 16),
+@pytest.mark.parametrize("threads,blocks,copies,unroll", [
+    (256, 0, 0, 0), (512, 0, 1, 2), (1024, 0, 32, 8), (256, 1, 4, 4), (512, 7, 2, 8),
+    (1024, 300, 8, 2), (256, 4096, 16, 4), (256, 3, 1, 8),
 ])
-def test_launch_shapes_agree(cs, tiny, threads, blocks, copies):
+def test_launch_shapes_agree(cs, tiny, threads, blocks, copies, unroll):
     t, host = tiny
     ref = oracle.stats(host)
     want = oracle.hist(host, ref.min, ref.max, 256)
-    cs.cube_set_launch(threads, blocks, copies)
+    cs.cube_set_launch(threads, blocks, copies, unroll)
     try:
         st, c = cs.stats_hist(t, ref.min, ref.max, 256)
         st2, c2 = cs.stats_hist_minmax(t, 256)
     finally:
-        cs.cube_set_launch(0, 0, 0)
+        cs.cube_set_launch(0, 0, 0, 0)
     assert_counts_match(c, want, "fused")
     assert_counts_match(c2, want, "minmax")
     assert_stats_match(st, ref, "fused")

@@ -1,0 +1,136 @@
+"""The query server (GPU): results in a concurrent mix equal the same query
+alone, and the plain mode agrees with the batched mode."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import assert_counts_match, assert_stats_match
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import paper_1111_6661_amd as cs
+    assert torch.cuda.is_available()
+    cs.load()
+    return cs
+
+
+@pytest.fixture(scope="module")
+def cubes():
+    import synth
+    rs = synth.serve_recipes(scale_div=16)[:6]
+    return [synth.cube_tensor(r, 300 + i, device="cuda") for i, r in enumerate(rs)]
+
+
+def random_queries(cs, cubes, n, seed, nbins_max=1024):
+    """(query, cube index, box slices, kind, nbins, lo, hi) of a random mix."""
+    rng = np.random.default_rng(seed)
+    out = torch.zeros((n, 64), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros((n, nbins_max + 3), dtype=torch.int64, device="cuda")
+    specs = []
+    for i in range(n):
+        c = int(rng.integers(len(cubes)))
+        t = cubes[c]
+        nz, ny, nx = t.shape
+        if rng.random() < 0.4:
+            sl = np.s_[:, :, :]
+        else:
+            z0, y0, x0 = (int(rng.integers(0, max(1, s // 2))) for s in (nz, ny, nx))
+            z1 = int(rng.integers(z0 + 1, nz + 1))
+            y1 = int(rng.integers(y0 + 1, ny + 1))
+            x1 = int(rng.integers(x0 + 1, nx + 1))
+            sl = np.s_[z0:z1, y0:y1, x0:x1]
+        kind = int(rng.choice([cs.CUBE_Q_STATS, cs.CUBE_Q_HIST, cs.CUBE_Q_FUSED, cs.CUBE_Q_MINMAX]))
+        nb = int(rng.choice([64, 256, 1024]))
+        lo, hi = float(rng.uniform(-4, -1)), float(rng.uniform(1, 30))
+        ptr, d = cs.box_of(t[sl])
+        q = cs.make_query(ptr, d, kind, nb, lo, hi, out[i].data_ptr(), cnt[i].data_ptr())
+        specs.append((q, c, sl, kind, nb, lo, hi))
+    return specs, out, cnt
+
+
+def test_server_mix_equals_alone(cs, cubes):
+    specs, out, cnt = random_queries(cs, cubes, 60, seed=3)
+    srv = cs.Server(cs.CUBE_SERVE_BATCHED, slots=3, max_batch=8, tile_voxels=1 << 16)
+    # submit from two threads with staggered arrivals
+    ids = [None] * len(specs)
+
+    def submitter(part):
+        for i in part:
+            ids[i] = srv.submit(specs[i][0])
+            time.sleep(0.0005)
+
+    th = [threading.Thread(target=submitter, args=(range(k, len(specs), 2),)) for k in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    lat = [srv.wait(i, timeout_s=60) for i in ids]
+    assert all(x >= 0 for x in lat)
+    p50, p99, n = srv.latency()
+    assert n == len(specs) and p99 >= p50 > 0
+    srv.close()
+    torch.cuda.synchronize()
+    # each query alone through its own batch gives the same bits
+    for i, (q, c, sl, kind, nb, lo, hi) in enumerate(specs):
+        o1 = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        c1 = torch.zeros(nb + 3, dtype=torch.int64, device="cuda")
+        q1 = cs.make_query(q.ptr, list(q.dims), kind, nb, lo, hi, o1.data_ptr(), c1.data_ptr())
+        b = cs.Batch(tile_voxels=1 << 16)
+        b.enqueue([q1])
+        b.check()
+        b.close()
+        if kind != cs.CUBE_Q_HIST:
+            assert torch.equal(o1, out[i]), f"query {i} stats differ alone vs in the mix"
+        if kind != cs.CUBE_Q_STATS:
+            assert torch.equal(c1, cnt[i, :nb + 3]), f"query {i} counts differ"
+    # and a sample agrees with the oracle
+    for i in range(0, len(specs), 7):
+        q, c, sl, kind, nb, lo, hi = specs[i]
+        host = cubes[c].cpu().numpy()[sl]
+        ref = oracle.stats(host)
+        if kind != cs.CUBE_Q_HIST:
+            st = cs.Stats.from_bytes(out[i].cpu().numpy().tobytes())
+            assert_stats_match(st, ref, f"query {i}")
+        got = cnt[i, :nb + 3].cpu().numpy().view(np.uint64)
+        if kind in (cs.CUBE_Q_HIST, cs.CUBE_Q_FUSED):
+            assert_counts_match(got, oracle.hist(host, lo, hi, nb), f"query {i}")
+        elif kind == cs.CUBE_Q_MINMAX and ref.n_valid:
+            assert_counts_match(got, oracle.hist(host, ref.min, ref.max, nb), f"query {i}")
+
+
+def test_plain_mode_agrees(cs, cubes):
+    specs, out, cnt = random_queries(cs, cubes, 20, seed=4)
+    srv = cs.Server(cs.CUBE_SERVE_PLAIN)
+    ids = [srv.submit(s[0]) for s in specs]
+    for i in ids:
+        srv.wait(i, timeout_s=60)
+    srv.close()
+    for i, (q, c, sl, kind, nb, lo, hi) in enumerate(specs):
+        host = cubes[c].cpu().numpy()[sl]
+        ref = oracle.stats(host)
+        if kind != cs.CUBE_Q_HIST:
+            assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref, f"q{i}")
+        got = cnt[i, :nb + 3].cpu().numpy().view(np.uint64)
+        if kind in (cs.CUBE_Q_HIST, cs.CUBE_Q_FUSED):
+            assert_counts_match(got, oracle.hist(host, lo, hi, nb), f"q{i}")
+
+
+def test_server_rejects_bad_queries(cs, cubes):
+    srv = cs.Server()
+    t = cubes[0]
+    ptr, d = cs.box_of(t)
+    o = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(cs.CubeError):
+        srv.submit(cs.make_query(ptr, d, 7, 8, 0, 1, o.data_ptr(), o.data_ptr()))
+    with pytest.raises(cs.CubeError):
+        srv.submit(cs.make_query(ptr, d, cs.CUBE_Q_HIST, 8, 1, 0, 0, o.data_ptr()))
+    with pytest.raises(cs.CubeError):
+        srv.wait(12345, timeout_s=0.01)
+    srv.close()
