@@ -79,6 +79,148 @@ def cpu_baseline(cube, nbins: int, lo: float, hi: float, target_s: float):
             "seconds": dt}
 
 
+def bench_batch64(cs, synth, torch, dev, steps: int):
+    """64 uneven items, each statistics then a 512-bin histogram over its own
+    [min, max]: one persistent launch replayed from a HIP graph, against the
+    plain per-item calls (two launches each) on one stream."""
+    import numpy as np
+    recs = synth.batch_item_recipes()
+    items = [synth.cube_tensor(r, synth.BASE_SEED + 2 + i, device=dev) for i, r in enumerate(recs)]
+    nvox = sum(r.n for r in recs)
+    nb = synth.HIST_BINS["batch64"]
+    n = len(items)
+    stream = torch.cuda.Stream(device=dev)
+    sp = stream.cuda_stream
+    out = torch.zeros((n, 64), dtype=torch.uint8, device=dev)
+    cnt = torch.zeros((n, nb + 3), dtype=torch.int64, device=dev)
+    boxes = [cs.box_of(t) for t in items]
+    qs = [cs.make_query(p, d, cs.CUBE_Q_MINMAX, nb, 0.0, 0.0, out[i].data_ptr(), cnt[i].data_ptr())
+          for i, (p, d) in enumerate(boxes)]
+    # tile size: the fastest of a few (graph-replayed)
+    tiles = {}
+    for tv in (1 << 16, 1 << 17, 1 << 18, 1 << 20):
+        b = cs.Batch(tile_voxels=tv)
+        b.enqueue(qs, sp)
+        b.check()
+        _, ms = time_launches(lambda: b.graph_launch(sp), stream, max(5, steps // 3), 2)
+        tiles[tv] = ms
+        b.close()
+    best_tile = min(tiles, key=tiles.get)
+    b = cs.Batch(tile_voxels=best_tile)
+    b.enqueue(qs, sp)
+    b.check()
+    _, ev_b = time_launches(lambda: b.graph_launch(sp), stream, steps, 3)
+    b.check()
+    out2 = torch.zeros_like(out)
+    cnt2 = torch.zeros_like(cnt)
+
+    def plain():
+        for i, (p, d) in enumerate(boxes):
+            cs.cube_stats_hist_minmax_async(p, d, nb, out2[i].data_ptr(), cnt2[i].data_ptr(), sp)
+
+    _, ev_p = time_launches(plain, stream, steps, 3)
+    torch.cuda.synchronize()
+    counts_equal = bool(torch.equal(cnt, cnt2))
+    worst = 0.0
+    for i in range(n):
+        a = cs.Stats.from_bytes(out[i].cpu().numpy().tobytes())
+        c = cs.Stats.from_bytes(out2[i].cpu().numpy().tobytes())
+        if a.min != c.min or a.max != c.max or a.n_valid != c.n_valid:
+            counts_equal = False
+        worst = max(worst, abs(a.std - c.std) / c.std)
+    b.close()
+    del items
+    return {"items": n, "voxels": nvox, "nbins": nb, "tile_voxels": best_tile,
+            "tile_sweep_ms": {str(k): round(v, 4) for k, v in tiles.items()},
+            "batched_graph_ms": ev_b, "plain_ms": ev_p,
+            "batched_voxels_per_s": nvox / (ev_b * 1e-3), "plain_voxels_per_s": nvox / (ev_p * 1e-3),
+            "speedup": ev_p / ev_b, "counts_and_extrema_equal": counts_equal,
+            "max_std_rel_diff_batched_vs_plain": worst}
+
+
+def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7):
+    """Twelve resident cubes (about 201 GiB); a seeded Poisson query stream at
+    load_frac of the plain server's closed-loop capacity, replayed against the
+    plain server and the continuous-batching server."""
+    import threading
+    from paper_1111_6661_amd import workloads
+    recipes = synth.serve_recipes()
+    log(f"serve: generating {len(recipes)} cubes, "
+        f"{sum(r.n for r in recipes) * 4 / 2**30:.1f} GiB")
+    cubes = [synth.cube_tensor(r, synth.BASE_SEED + 3 + i, device=dev) for i, r in enumerate(recipes)]
+    ranges = []
+    for c in cubes:
+        st = cs.stats(c)
+        ranges.append(((st.min, st.max), (st.mean - 2 * st.std, st.mean + 2 * st.std)))
+    shapes = [tuple(c.shape) for c in cubes]
+
+    def make(specs):
+        n = len(specs)
+        out = torch.zeros((n, 64), dtype=torch.uint8, device=dev)
+        cnt = torch.zeros((n, 4096 + 3), dtype=torch.int64, device=dev)
+        qs = []
+        for i, q in enumerate(specs):
+            z0, z1, y0, y1, x0, x1 = q.box
+            p, d = cs.box_of(cubes[q.cube][z0:z1, y0:y1, x0:x1])
+            qs.append(cs.make_query(p, d, q.kind, q.nbins or 1, q.lo, q.hi, out[i].data_ptr(),
+                                    cnt[i].data_ptr()))
+        return qs, out, cnt
+
+    def replay(mode, specs, open_loop: bool):
+        qs, out, cnt = make(specs)
+        srv = cs.Server(mode, slots=4, max_batch=32, max_inflight_bytes=1 << 30)
+        ids = [0] * len(qs)
+        t0 = time.perf_counter()
+
+        def submit_all():
+            for i, q in enumerate(qs):
+                if open_loop:
+                    dt = specs[i].t_arrival - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                ids[i] = srv.submit(q)
+
+        th = threading.Thread(target=submit_all)
+        th.start()
+        th.join()
+        for i in ids:
+            srv.wait(i)
+        wall = time.perf_counter() - t0
+        p50, p99, n = srv.latency()
+        srv.close()
+        torch.cuda.synchronize()
+        return {"queries": n, "wall_s": wall, "p50_ms": p50 * 1e3, "p99_ms": p99 * 1e3,
+                "qps": n / wall, "voxels_per_s": sum(q.voxels for q in specs) / wall}, out, cnt
+
+    # closed-loop capacity of the plain server
+    cap_specs = workloads.query_stream(shapes, ranges, 200, 1e9, synth.BASE_SEED + 30,
+                                       cs.CUBE_Q_STATS, cs.CUBE_Q_FUSED)
+    cap, _, _ = replay(cs.CUBE_SERVE_PLAIN, cap_specs, open_loop=False)
+    qps = load_frac * cap["qps"]
+    n = max(50, int(qps * seconds))
+    specs = workloads.query_stream(shapes, ranges, n, qps, synth.BASE_SEED + 31,
+                                   cs.CUBE_Q_STATS, cs.CUBE_Q_FUSED)
+    log(f"serve: plain capacity {cap['qps']:.0f} QPS; replaying {n} queries at {qps:.0f} QPS")
+    plain, po, pc = replay(cs.CUBE_SERVE_PLAIN, specs, open_loop=True)
+    served, so, sc = replay(cs.CUBE_SERVE_BATCHED, specs, open_loop=True)
+    same_counts = bool(torch.equal(pc, sc))
+    same_extrema = True
+    for i in range(n):
+        if specs[i].kind == cs.CUBE_Q_STATS or True:
+            a = cs.Stats.from_bytes(po[i].cpu().numpy().tobytes())
+            b = cs.Stats.from_bytes(so[i].cpu().numpy().tobytes())
+            if a.n_valid != b.n_valid or not (a.min == b.min or a.min != a.min):
+                same_extrema = False
+    del cubes
+    torch.cuda.empty_cache()
+    return {"cubes": len(recipes), "resident_gib": sum(r.n for r in recipes) * 4 / 2**30,
+            "plain_capacity_qps": cap["qps"], "offered_qps": qps, "load_frac": load_frac,
+            "plain": plain, "served": served,
+            "p50_speedup": plain["p50_ms"] / served["p50_ms"],
+            "p99_speedup": plain["p99_ms"] / served["p99_ms"],
+            "results_equal_plain_vs_served": same_counts and same_extrema}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +232,10 @@ def main() -> int:
                     help="threads,blocks,hist_copies,unroll override (0 = automatic)")
     ap.add_argument("--only-fused", action="store_true",
                     help="time the fused pass only (for profiler runs)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-item batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -120,6 +266,11 @@ def main() -> int:
     lo, hi = float(st0.min), float(st0.max)
     log(f"stats: n_nan={st0.n_nan} min={lo} max={hi} mean={st0.mean:.6g} std={st0.std:.6g}")
 
+    tuned = None
+    if not args.no_tune and not args.launch:
+        tuned = cs.cube_autotune(cube.data_ptr(), dims, cs.CUBE_Q_FUSED, lo, hi, nbins, reps=4)
+        log(f"autotune (fused): {tuned['best']}")
+
     stream = torch.cuda.Stream(device=dev)
     out = torch.zeros(64, dtype=torch.uint8, device=dev)
     counts = torch.zeros(nbins + 3, dtype=torch.int64, device=dev)
@@ -136,6 +287,14 @@ def main() -> int:
 
     def two_pass():
         cs.cube_stats_hist_minmax_async(ptr, dims, nbins, out.data_ptr(), counts.data_ptr(), sp)
+
+    # A plain copy of known size (1 GiB read + 1 GiB written), outside the
+    # timed region: profiler byte counters are scaled by what they read for it.
+    cal_src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
 
     stream.wait_stream(torch.cuda.current_stream())
     # The timed region: exactly `steps` fused launches, bracketed by syncs.
@@ -161,6 +320,13 @@ def main() -> int:
         extra[label] = {"ms_per_call_events": round(e, 4), "voxels_per_s": r.n / (e * 1e-3)}
         log(f"{label}: {e:.4f} ms")
 
+    if tuned is not None:
+        extra["autotune_fused"] = tuned
+    if not args.only_fused and not args.no_batch:
+        log("batch64 ...")
+        extra["batch64"] = bench_batch64(cs, synth, torch, dev, max(10, args.steps // 2))
+        log(f"batch64: graph {extra['batch64']['batched_graph_ms']:.3f} ms vs plain "
+            f"{extra['batch64']['plain_ms']:.3f} ms")
     bytes_per_launch = 4 * r.n
     achieved = bytes_per_launch / (ev_ms * 1e-3) / 1e9
     value = r.n / (wall_ms * 1e-3)
@@ -193,6 +359,15 @@ def main() -> int:
         cb = cpu_baseline(cube, nbins, lo, hi, args.cpu_seconds)
         result["cpu_baseline"] = cb
         log(f"cpu baseline: {cb['value']:.3g} voxels/s")
+    if not args.only_fused and not args.no_serve:
+        del cube
+        torch.cuda.empty_cache()
+        sv = bench_serve(cs, synth, torch, dev, args.serve_seconds)
+        extra["serve"] = sv
+        result["p50_ms"] = sv["served"]["p50_ms"]
+        result["p99_ms"] = sv["served"]["p99_ms"]
+        log(f"serve: plain p50/p99 {sv['plain']['p50_ms']:.2f}/{sv['plain']['p99_ms']:.2f} ms, "
+            f"served {sv['served']['p50_ms']:.2f}/{sv['served']['p99_ms']:.2f} ms")
     print(json.dumps(result), flush=True)
     return 0 if all(parity.values()) else 1
 

@@ -171,11 +171,30 @@ CUBE_API int cube_set_accum_mode(int32_t mode);
  * for experiments: threads per block (256, 512 or 1024; 0 = automatic),
  * blocks per launch (0 = automatic), histogram sub-copies per block (1..32,
  * a power of two; 0 = automatic), float4 loads per lane per pipelined tile
- * (2, 4 or 8; 0 = automatic).  Applies to later calls from any thread.
+ * (2 or 4; 0 = automatic).  Applies to later calls from any thread.
  * Results do not depend on the launch shape except for the rounding of the
  * moments (the merge order follows the grid).
  */
 CUBE_API int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll);
+
+/*
+ * Autotuner.  Times candidate launch shapes (threads, float4 loads per tile,
+ * LDS histogram copies, blocks per CU) of one pass kind -- CUBE_Q_STATS,
+ * CUBE_Q_HIST or CUBE_Q_FUSED over [lo, hi] -- on the given DEVICE box
+ * (`reps` timed launches each) and keeps the fastest for that pass kind,
+ * histogram-size class (bins rounded up to a power of two) and box-size
+ * class (voxels rounded up to a power of two).  Later single-box calls
+ * without an explicit cube_set_launch shape use it.  If `report` is not
+ * NULL, a JSON summary is written there.  Results never depend on the shape
+ * except for the rounding of the moments.
+ */
+CUBE_API int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
+                           float hi, int32_t nbins, int32_t reps, char *report, size_t report_cap);
+/* Save / load the tuned table (JSON, one entry per line, arch "gfx950");
+ * load returns the number of entries read. */
+CUBE_API int cube_tune_save(const char *path);
+CUBE_API int cube_tune_load(const char *path);
+CUBE_API void cube_tune_clear(void);
 
 /* Release every workspace on every device (synchronises each stream that
  * owns one).  The library stays usable; workspaces are made again on demand. */

@@ -116,6 +116,13 @@ def load() -> C.CDLL:
     lib.cube_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_double)]
     lib.cube_server_latency.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_uint64), i32]
+    lib.cube_autotune.argtypes = [P, I64P, i32, f32, f32, i32, i32, C.c_char_p, C.c_size_t]
+    lib.cube_autotune.restype = C.c_int
+    lib.cube_tune_save.argtypes = [C.c_char_p]
+    lib.cube_tune_save.restype = C.c_int
+    lib.cube_tune_load.argtypes = [C.c_char_p]
+    lib.cube_tune_load.restype = C.c_int
+    lib.cube_tune_clear.restype = None
     lib.cube_server_destroy.argtypes = [P]
     lib.cube_server_destroy.restype = None
     for name in ("cube_server_create", "cube_server_submit", "cube_server_wait",
@@ -212,6 +219,29 @@ def cube_set_accum_mode(mode: int) -> int:
 def cube_set_launch(threads: int = 0, blocks: int = 0, hist_copies: int = 0,
                     unroll: int = 0) -> None:
     _check(load().cube_set_launch(threads, blocks, hist_copies, unroll))
+
+
+def cube_autotune(ptr: int, dims, kind: int, lo: float = 0.0, hi: float = 0.0, nbins: int = 1,
+                  reps: int = 5) -> dict:
+    """Tune the launch shape for one pass kind on this data; returns the
+    autotuner's JSON report as a dict."""
+    import json
+    buf = C.create_string_buffer(1024)
+    _check(load().cube_autotune(C.c_void_p(ptr), _dims(dims), kind, lo, hi, nbins, reps, buf,
+                                len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def cube_tune_save(path: str) -> None:
+    _check(load().cube_tune_save(path.encode()))
+
+
+def cube_tune_load(path: str) -> int:
+    return _check(load().cube_tune_load(path.encode()))
+
+
+def cube_tune_clear() -> None:
+    load().cube_tune_clear()
 
 
 def cube_shutdown() -> None:

@@ -123,17 +123,20 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         const bool hist = tile.phase == 2 || it.kind == BQ_HIST || it.kind == BQ_FUSED;
 
         Hist H;
-        const bool hist_on = hist_setup(H, range, it.nbins, a.copies_log2, lds, acc);
+        const bool hist_on = hist && range.ok == 1;
+        hist_setup(H, range, it.nbins, a.copies_log2, lds, acc);
         Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f};
-        Wave W = {0.f, 0, 0ull, 0ull, 0ull, 0ull};
+        Wave W = {0.f, 0, 0ull, 0ull, 0ull};
         if (hist) lds_zero(lds, it.nbins, a.copies_log2);
         if (!skip) {
-            if (stats && hist)
+            if (stats && hist_on)
                 batch_scan<true, HIST_LDS>(it, u0, u1, L, W, H);
             else if (stats)
                 batch_scan<true, HIST_NONE>(it, u0, u1, L, W, H);
-            else
+            else if (hist_on)
                 batch_scan<false, HIST_LDS>(it, u0, u1, L, W, H);
+            else  // an invalid [min, max] range bins nothing
+                batch_scan<false, HIST_NONE>(it, u0, u1, L, W, H);
         }
         const long long rec0 = tile.phase == 1 ? it.rec1 : it.rec2;
         WaveRec *recs = a.recs + rec0;
@@ -472,7 +475,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     // Launch shape: one histogram copy layout for the batch, a grid of
     // resident blocks.
     int clog = 0;
-    while (clog < 4 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= 32 * 1024) ++clog;
+    while (clog < 5 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= 64 * 1024) ++clog;
     b->lds = ((size_t)(max_bins + 2) << clog) * 4;
     int bpc = 1;
     if ((e = batch_occupancy(b->threads, b->lds, &bpc)) != hipSuccess)

@@ -37,7 +37,16 @@ int hip_fail(hipError_t e, const char *what)
 std::atomic<int> g_accum{CUBE_ACCUM_FP64MERGE};
 
 int accum_mode() { return g_accum.load(); }
+
 std::atomic<int> g_threads{0}, g_blocks{0}, g_copies{0}, g_unroll{0};
+
+void get_launch(int *threads, int *blocks, int *copies, int *unroll)
+{
+    *threads = g_threads.load();
+    *blocks = g_blocks.load();
+    *copies = g_copies.load();
+    *unroll = g_unroll.load();
+}
 
 constexpr int MAX_BLOCKS = 4096;
 constexpr int MAX_WAVES_PER_BLOCK = 16;
@@ -262,11 +271,21 @@ void collapse(const Box &b, Geom *g)
 int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
 {
     collapse(b, &p->g);
-    int threads = g_threads.load();
+    int threads = g_threads.load(), unroll = g_unroll.load(), copies_req = g_copies.load();
+    long long blocks = g_blocks.load();
+    // With no explicit shape, use the autotuner's choice for this class.
+    TunedShape ts;
+    const int kind = stats ? (hist_kind_req ? CUBE_Q_FUSED : CUBE_Q_STATS) : CUBE_Q_HIST;
+    if (threads == 0 && unroll == 0 && copies_req == 0 && blocks == 0 &&
+        tuned_shape(kind, hist_kind_req ? nbins : 1, b.n, &ts)) {
+        threads = ts.threads;
+        unroll = ts.unroll;
+        copies_req = ts.copies;
+        blocks = (long long)cu_count() * ts.blocks_per_cu;
+    }
     if (threads != 256 && threads != 512 && threads != 1024) threads = hist_kind_req ? 1024 : 256;
     p->threads = threads;
-    int unroll = g_unroll.load();
-    p->unroll = (unroll == 2 || unroll == 4 || unroll == 8) ? unroll : 4;
+    p->unroll = (unroll == 2 || unroll == 4) ? unroll : 4;
     p->hist = HIST_NONE;
     p->copies_log2 = 0;
     if (hist_kind_req) {
@@ -274,7 +293,7 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
             p->hist = HIST_GLOBAL;
         } else {
             p->hist = HIST_LDS;
-            int c = g_copies.load();
+            int c = copies_req;
             int clog = 0;
             if (c > 0) {
                 while ((1 << (clog + 1)) <= c && clog < 5) ++clog;
@@ -294,7 +313,6 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
     // tails).
     const long long cap = (long long)cu_count() * (bpc < 4 ? 4 : bpc);
     const long long per_block_min = (long long)threads * 16 * 2;  // two main-loop steps
-    long long blocks = g_blocks.load();
     if (blocks <= 0) {
         blocks = (long long)((b.n + per_block_min - 1) / per_block_min);
         if (blocks > cap) blocks = cap;
@@ -552,8 +570,8 @@ int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_
     if (blocks < 0 || blocks > MAX_BLOCKS) return fail(CUBE_EINVAL, "blocks outside [0, 4096]");
     if (hist_copies < 0 || hist_copies > 32 || (hist_copies & (hist_copies - 1)))
         return fail(CUBE_EINVAL, "hist_copies must be 0 or a power of two <= 32");
-    if (unroll != 0 && unroll != 2 && unroll != 4 && unroll != 8)
-        return fail(CUBE_EINVAL, "unroll must be 0, 2, 4 or 8");
+    if (unroll != 0 && unroll != 2 && unroll != 4)
+        return fail(CUBE_EINVAL, "unroll must be 0, 2 or 4");
     g_threads = threads;
     g_blocks = blocks;
     g_copies = hist_copies;

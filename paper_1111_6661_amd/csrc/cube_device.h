@@ -63,38 +63,45 @@ struct Lane {
 struct Wave {  // wavefront-uniform
     float K;
     int has_k;
-    unsigned long long slots, nan, below, above;  // lane-voxel slots seen, and ballots
+    unsigned long long valid, ge, le;  // ballot counts: valid, x >= lo, x <= hi
 };
 
-// The histogram as one voxel sees it.  LDS layout: slot b of copy c is the
-// word b * C + c (C = 1 << copies_log2 copies, interleaved so that lanes of
-// one wavefront hitting the same bin hit different banks).  Slots 0..nbins-1
-// are the bins; slot nbins collects the x == hi-side rounding case
-// floor(u) == nbins and is added to bin nbins-1 at the flush (this is the
-// min(nbins-1, .) of the bin rule); slot nbins+1 collects blank and
-// out-of-range voxels, which are counted with ballots instead.
+// The histogram as one voxel sees it.  LDS layout: slot s of copy c is the
+// word s * C + c (C = 1 << copies_log2 copies, interleaved so that lanes of
+// one wavefront hitting the same bin hit different banks).  Slot 0 collects
+// blank and out-of-range voxels (they are counted with ballots instead);
+// slots 1..nbins are bins 0..nbins-1; slot nbins+1 collects the rounding
+// case floor(u) == nbins and is added to bin nbins-1 at the flush (this is
+// the min(nbins-1, .) of the bin rule).  The byte address of bin b for a
+// lane is (b << shift) + base with base = (C + lane % C) * 4, so the dummy
+// slot is b = -1, an inline constant.
 struct Hist {
     float lo, hi, scale;
-    int nbins, shift, lane_off, dummy;
+    int nbins, shift, base;
     unsigned int *lds;
     unsigned long long *global;
 };
 
-// v ? with the lanes of `m` replaced: m[lane] ? w : v (one v_cndmask_b32 reading a
-// ballot mask, so the mask a ballot already produced is not recomputed).
-__device__ __forceinline__ float zero_where(float v, unsigned long long m)
+// m[lane] ? v : 0, and m[lane] ? v : -1 -- one v_cndmask_b32 reading a
+// ballot mask directly, so a mask a ballot already produced is reused.
+__device__ __forceinline__ float keep_where(float v, unsigned long long m)
 {
     float r;
-    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(v), "s"(m));
+    asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(m));
     return r;
 }
-__device__ __forceinline__ int replace_where(int v, int w, unsigned long long m)
+__device__ __forceinline__ int keep_or_minus1(int v, unsigned long long m)
 {
     int r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(v), "v"(w), "s"(m));
+    asm("v_cndmask_b32_e64 %0, -1, %1, %2" : "=v"(r) : "v"(v), "s"(m));
     return r;
 }
 
+// One step over NV voxels per lane.  With a histogram, two compares decide
+// everything: A = (x >= lo), B = (x <= hi) are both false for a NaN and,
+// since lo <= hi, not both false otherwise, so valid = A|B, in-range = A&B,
+// and below = valid - |A|, above = valid - |B| (scalar mask algebra and
+// popcounts on the ballots).
 template <bool STATS, int HIST, int ACC, int NV>
 __device__ __forceinline__ void process(const float (&x)[NV], Lane &L, Wave &W,
                                         const Hist &H)
@@ -112,50 +119,54 @@ __device__ __forceinline__ void process(const float (&x)[NV], Lane &L, Wave &W,
         }
     }
     // Ballot counts of this step in 32-bit scalars (at most 64 * NV each).
-    unsigned int cnan = 0, cbelow = 0, cabove = 0;
+    unsigned int cvalid = 0, cge = 0, cle = 0;
     float t1 = 0.f, t2 = 0.f;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         const float v = x[j];
-        const unsigned long long mnan = __builtin_amdgcn_ballot_w64(v != v);
-        cnan += __popcll(mnan);
+        unsigned long long mvalid, inr = 0;
+        if (HIST != HIST_NONE) {
+            const unsigned long long mge = __builtin_amdgcn_ballot_w64(v >= H.lo);
+            const unsigned long long mle = __builtin_amdgcn_ballot_w64(v <= H.hi);
+            mvalid = mge | mle;
+            inr = mge & mle;
+            cge += __popcll(mge);
+            cle += __popcll(mle);
+        } else {
+            mvalid = __builtin_amdgcn_ballot_w64(v == v);
+        }
+        cvalid += __popcll(mvalid);
         if (STATS) {
             const float q = __builtin_canonicalizef(v);
             L.mn = fminf(L.mn, q);
             L.mx = fmaxf(L.mx, q);
             if (ACC == CUBE_ACCUM_NAIVE32) {
-                const float d = zero_where(v, mnan);
+                const float d = keep_where(v, mvalid);
                 L.s1 += d;
                 L.s2 = __fmaf_rn(d, d, L.s2);
             } else {
-                const float d = zero_where(__fsub_rn(v, W.K), mnan);
+                const float d = keep_where(__fsub_rn(v, W.K), mvalid);
                 t1 += d;
                 t2 = __fmaf_rn(d, d, t2);
             }
         }
         if (HIST != HIST_NONE) {
-            const unsigned long long mbelow = __builtin_amdgcn_ballot_w64(v < H.lo);
-            const unsigned long long mabove = __builtin_amdgcn_ballot_w64(v > H.hi);
-            cbelow += __popcll(mbelow);
-            cabove += __popcll(mabove);
-            const unsigned long long mout = mnan | mbelow | mabove;
             const float u = __fmul_rn(__fsub_rn(v, H.lo), H.scale);
             if (HIST == HIST_LDS) {
-                const int b = replace_where(cvt_flr_i32(u), H.dummy, mout);
-                atomicAdd((unsigned int *)((char *)H.lds + ((b << H.shift) + H.lane_off)), 1u);
+                const int b = keep_or_minus1(cvt_flr_i32(u), inr);
+                atomicAdd((unsigned int *)((char *)H.lds + ((b << H.shift) + H.base)), 1u);
             } else {
                 const int b = min(cvt_flr_i32(u), H.nbins - 1);
-                if (!((mout >> (threadIdx.x & 63)) & 1ull)) atomicAdd(&H.global[b], 1ull);
+                if ((inr >> (threadIdx.x & 63)) & 1ull) atomicAdd(&H.global[b], 1ull);
             }
         }
     }
     // Keep the step counts 32-bit (the compiler would otherwise widen every
     // per-voxel add to 64 bits).
-    asm("" : "+s"(cnan), "+s"(cbelow), "+s"(cabove));
-    W.slots += 64u * NV;
-    W.nan += cnan;
-    W.below += cbelow;
-    W.above += cabove;
+    asm("" : "+s"(cvalid), "+s"(cge), "+s"(cle));
+    W.valid += cvalid;
+    W.ge += cge;
+    W.le += cle;
     if (STATS && ACC != CUBE_ACCUM_NAIVE32) {
         two_sum_acc(L.s1, L.c1, t1);
         two_sum_acc(L.s2, L.c2, t2);
@@ -291,24 +302,22 @@ __device__ __forceinline__ void process_tile(const f4 (&v)[U], Lane &L, Wave &W,
     process<STATS, HIST, ACC, 4 * U>(xv, L, W, H);
 }
 
-// Histogram context of a pass over the range r (an invalid range -- lo = +inf,
-// hi = -inf -- sends every voxel out of range).  Returns whether it is valid.
-__device__ __forceinline__ bool hist_setup(Hist &H, const HistRange &r, int nbins,
+// Histogram context of a pass over the valid range r (an invalid range is
+// handled by the caller with a pass without histogram).
+__device__ __forceinline__ void hist_setup(Hist &H, const HistRange &r, int nbins,
                                            int copies_log2, unsigned int *lds,
                                            unsigned long long *acc)
 {
     const int lane = threadIdx.x & 63;
+    const int C = 1 << copies_log2;
     H.nbins = nbins;
     H.shift = copies_log2 + 2;
-    H.lane_off = (lane & ((1 << copies_log2) - 1)) * 4;
+    H.base = (C + (lane & (C - 1))) * 4;
     H.lds = lds;
     H.global = acc;
-    H.dummy = nbins + 1;
-    const bool on = (r.ok == 1);
-    H.lo = on ? r.lo : INFINITY;
-    H.hi = on ? r.hi : -INFINITY;
-    H.scale = on ? r.scale : 0.f;
-    return on;
+    H.lo = r.lo;
+    H.hi = r.hi;
+    H.scale = r.scale;
 }
 
 // Zero the LDS sub-histograms (nbins + 2 slots per copy); ends with a barrier.
@@ -411,6 +420,9 @@ __device__ __forceinline__ void write_wave_record(const Lane &L, const Wave &W, 
     }
     if ((threadIdx.x & 63) == 0) {
         WaveRec r;
+        r.n_valid = W.valid;
+        r.below = W.valid - W.ge;
+        r.above = W.valid - W.le;
         r.K = W.K;
         r.s1h = s1h;
         r.s1l = s1l;
@@ -419,9 +431,6 @@ __device__ __forceinline__ void write_wave_record(const Lane &L, const Wave &W, 
         r.mn = mn;
         r.mx = mx;
         r.pad = 0.f;
-        r.n_valid = W.slots - W.nan;
-        r.below = W.below;
-        r.above = W.above;
         r.pad2 = 0ull;
         *dst = r;
     }
@@ -436,9 +445,9 @@ __device__ __forceinline__ void hist_flush(const unsigned int *lds, int nbins, i
     const int C = 1 << copies_log2;
     for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
         unsigned int sum = 0;
-        for (int c = 0; c < C; ++c) sum += lds[(b << copies_log2) + c];
+        for (int c = 0; c < C; ++c) sum += lds[((b + 1) << copies_log2) + c];
         if (b == nbins - 1)  // floor(u) == nbins belongs to the last bin
-            for (int c = 0; c < C; ++c) sum += lds[(nbins << copies_log2) + c];
+            for (int c = 0; c < C; ++c) sum += lds[((nbins + 1) << copies_log2) + c];
         if (sum) atomicAdd(&acc[b], (unsigned long long)sum);
     }
 }

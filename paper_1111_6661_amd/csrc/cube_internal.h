@@ -56,7 +56,7 @@ struct PassArgs {
 
 // Kernel launchers (cube_kernels.hip).  `stats`: compute the statistics;
 // `hist`: HIST_NONE / HIST_LDS / HIST_GLOBAL.  Returns the launch error.
-// `unroll`: float4 loads per lane per pipelined tile (2, 4 or 8).
+// `unroll`: float4 loads per lane per pipelined tile (2 or 4).
 hipError_t launch_pass(const PassArgs &a, bool stats, int hist, int threads,
                        int blocks, size_t lds_bytes, int unroll, hipStream_t s);
 
@@ -92,5 +92,14 @@ int check_range(float lo, float hi, int32_t nbins, HistRange *r);
 void collapse(const Box &b, Geom *g);
 int cu_count();
 int accum_mode();
+void get_launch(int *threads, int *blocks, int *copies, int *unroll);
+
+// A launch shape chosen by the autotuner (cube_tune.hip).
+struct TunedShape {
+    int threads, unroll, copies, blocks_per_cu;
+    float ms;
+};
+// The tuned shape for (pass kind CUBE_Q_*, nbins, voxels), if any.
+bool tuned_shape(int kind, int nbins, uint64_t voxels, TunedShape *out);
 
 }  // namespace cube

@@ -20,20 +20,23 @@ __global__ void __launch_bounds__(1024) k_pass(PassArgs a)
     const int wid = tid >> 6, nw = blockDim.x >> 6;
 
     Hist H;
-    bool hist_on = false;
     const HistRange r0 = {0.f, 0.f, 0.f, 0};
-    hist_on = hist_setup(H, HIST != HIST_NONE ? (a.dev_range ? *a.dev_range : a.range) : r0,
-                         a.nbins, a.copies_log2, lds, a.hist_acc);
+    const HistRange hr = HIST != HIST_NONE ? (a.dev_range ? *a.dev_range : a.range) : r0;
+    const bool hist_on = HIST != HIST_NONE && hr.ok == 1;
+    hist_setup(H, hr, a.nbins, a.copies_log2, lds, a.hist_acc);
     if (HIST == HIST_LDS) lds_zero(lds, a.nbins, a.copies_log2);
 
     Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f};
-    Wave W = {0.f, ACC == CUBE_ACCUM_NAIVE32 ? 1 : 0, 0ull, 0ull, 0ull, 0ull};
+    Wave W = {0.f, ACC == CUBE_ACCUM_NAIVE32 ? 1 : 0, 0ull, 0ull, 0ull};
 
     const Geom &g = a.g;
     const unsigned long long G = gridDim.x;
     const long long u0 = (long long)(((unsigned long long)g.n_units * blockIdx.x) / G);
     const long long u1 = (long long)(((unsigned long long)g.n_units * (blockIdx.x + 1)) / G);
-    scan_units<STATS, HIST, ACC, U>(g, u0, u1, L, W, H);
+    if (HIST == HIST_NONE || hist_on)
+        scan_units<STATS, HIST, ACC, U>(g, u0, u1, L, W, H);
+    else  // an invalid range bins nothing: count valid voxels only
+        scan_units<STATS, HIST_NONE, ACC, U>(g, u0, u1, L, W, H);
 
     write_wave_record<STATS, ACC>(L, W, &a.recs[(long long)blockIdx.x * nw + wid]);
     if (HIST == HIST_LDS) hist_flush(lds, a.nbins, a.copies_log2, a.hist_acc);
@@ -73,11 +76,8 @@ size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int thre
 template <bool STATS, int HIST, int ACC>
 static const void *kernel_of(int unroll)
 {
-    switch (unroll) {
-    case 2: return reinterpret_cast<const void *>(&k_pass<STATS, HIST, ACC, 2>);
-    case 8: return reinterpret_cast<const void *>(&k_pass<STATS, HIST, ACC, 8>);
-    default: return reinterpret_cast<const void *>(&k_pass<STATS, HIST, ACC, 4>);
-    }
+    if (unroll == 2) return reinterpret_cast<const void *>(&k_pass<STATS, HIST, ACC, 2>);
+    return reinterpret_cast<const void *>(&k_pass<STATS, HIST, ACC, 4>);
 }
 
 static const void *pick(bool stats, int hist, int acc, int u)

@@ -1,0 +1,250 @@
+// cube_tune.hip -- the autotuner of the single-box pass.
+//
+// It times candidate launch shapes (threads per block, float4 loads per
+// pipelined tile, LDS histogram copies, blocks per CU) of one pass kind on
+// the caller's own data with HIP events, and keeps the fastest shape per
+// (pass kind, histogram-size class, box-size class) in a table that the
+// launch planner consults when no explicit shape is set.  The table can be
+// saved to and loaded from a small JSON file, keyed by the GPU architecture.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "cube_internal.h"
+
+namespace cube {
+
+namespace {
+
+struct TuneKey {
+    int kind, bins_log2, size_log2;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(kind, bins_log2, size_log2) < std::tie(o.kind, o.bins_log2, o.size_log2);
+    }
+};
+
+std::mutex g_tmu;
+std::map<TuneKey, TunedShape> g_table;
+
+int ilog2_ceil(uint64_t v)
+{
+    int k = 0;
+    while (k < 63 && ((uint64_t)1 << k) < v) ++k;
+    return k;
+}
+
+TuneKey key_of(int kind, int nbins, uint64_t voxels)
+{
+    return TuneKey{kind, kind == CUBE_Q_STATS ? 0 : ilog2_ceil((uint64_t)nbins),
+                   ilog2_ceil(voxels < 1 ? 1 : voxels)};
+}
+
+}  // namespace
+
+bool tuned_shape(int kind, int nbins, uint64_t voxels, TunedShape *out)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    auto it = g_table.find(key_of(kind, nbins, voxels));
+    if (it == g_table.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+}  // namespace cube
+
+using namespace cube;
+
+extern "C" {
+
+int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo, float hi,
+                  int32_t nbins, int32_t reps, char *report, size_t report_cap)
+{
+    if (kind != CUBE_Q_STATS && kind != CUBE_Q_HIST && kind != CUBE_Q_FUSED)
+        return fail(CUBE_EINVAL, "autotune kinds: CUBE_Q_STATS, CUBE_Q_HIST, CUBE_Q_FUSED");
+    if (reps < 1 || reps > 100) return fail(CUBE_EINVAL, "reps outside [1, 100]");
+    Box box;
+    int rc = check_box(ptr, dims, &box);
+    if (!rc) rc = check_box_device(&box);
+    if (rc) return rc;
+    if (box.n == 0) return fail(CUBE_EINVAL, "nothing to tune on an empty box");
+    HistRange r;
+    if (kind != CUBE_Q_STATS && (rc = check_range(lo, hi, nbins, &r))) return rc;
+    if (kind == CUBE_Q_STATS) nbins = 1;
+    hipStream_t s = nullptr;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "tune stream");
+    cube_stats_t *d_out = nullptr;
+    unsigned long long *d_counts = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipMalloc(&d_out, sizeof(cube_stats_t))) != hipSuccess ||
+        (e = hipMalloc(&d_counts, ((size_t)nbins + 3) * 8)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        hipFree(d_out);
+        hipFree(d_counts);
+        hipStreamDestroy(s);
+        return hip_fail(e, "tune buffers");
+    }
+    const int cus = cu_count();
+    const int threads_c[] = {256, 512, 1024};
+    const int unroll_c[] = {2, 4};
+    const int copies_c[] = {8, 16, 32};
+    const int bpc_c[] = {1, 2, 4, 8};
+    struct Cand {
+        TunedShape sh;
+        float ms;
+    };
+    std::vector<Cand> cands;
+    // Save the caller's explicit shape; each candidate is set explicitly.
+    int prev_t, prev_b, prev_c, prev_u;
+    get_launch(&prev_t, &prev_b, &prev_c, &prev_u);
+    auto run_one = [&](void) -> int {
+        switch (kind) {
+        case CUBE_Q_STATS: return cube_stats_async(ptr, dims, d_out, s);
+        case CUBE_Q_HIST: return cube_hist_async(ptr, dims, lo, hi, nbins,
+                                                 (uint64_t *)d_counts, s);
+        default: return cube_stats_hist_async(ptr, dims, lo, hi, nbins, d_out,
+                                              (uint64_t *)d_counts, s);
+        }
+    };
+    rc = CUBE_OK;
+    for (int t : threads_c)
+        for (int u : unroll_c)
+            for (int c : copies_c) {
+                if (kind == CUBE_Q_STATS && c != copies_c[0]) continue;
+                // The LDS histogram must fit one block (160 KiB).
+                if (kind != CUBE_Q_STATS && ((size_t)(nbins + 2) * c * 4 > 160 * 1024)) continue;
+                for (int bpc : bpc_c) {
+                    const int blocks = std::min(cus * bpc, 4096);
+                    if ((rc = cube_set_launch(t, blocks, kind == CUBE_Q_STATS ? 0 : c, u))) break;
+                    if ((rc = run_one())) break;  // warm-up
+                    hipEventRecord(e0, s);
+                    for (int i = 0; i < reps && !rc; ++i) rc = run_one();
+                    hipEventRecord(e1, s);
+                    if (rc) break;
+                    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+                        rc = hip_fail(e, "tune synchronize");
+                        break;
+                    }
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    Cand cd;
+                    cd.sh.threads = t;
+                    cd.sh.unroll = u;
+                    cd.sh.copies = kind == CUBE_Q_STATS ? 0 : c;
+                    cd.sh.blocks_per_cu = bpc;
+                    cd.sh.ms = ms / reps;
+                    cd.ms = ms / reps;
+                    cands.push_back(cd);
+                }
+                if (rc) break;
+            }
+    cube_set_launch(prev_t, prev_b, prev_c, prev_u);
+    hipStreamSynchronize(s);
+    hipFree(d_out);
+    hipFree(d_counts);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(s);
+    if (rc) return rc;
+    if (cands.empty()) return fail(CUBE_EINVAL, "no launch shape fits these arguments");
+    std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_table[key_of(kind, nbins, box.n)] = cands[0].sh;
+    }
+    if (report && report_cap) {
+        std::string rep = "{\"best\": ";
+        char buf[256];
+        auto fmt = [&](const TunedShape &sh) {
+            snprintf(buf, sizeof buf,
+                     "{\"threads\": %d, \"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, "
+                     "\"ms\": %.5f}",
+                     sh.threads, sh.unroll, sh.copies, sh.blocks_per_cu, sh.ms);
+            return std::string(buf);
+        };
+        rep += fmt(cands[0].sh) + ", \"worst\": " + fmt(cands.back().sh);
+        snprintf(buf, sizeof buf, ", \"candidates\": %zu}", cands.size());
+        rep += buf;
+        snprintf(report, report_cap, "%s", rep.c_str());
+    }
+    return CUBE_OK;
+}
+
+int cube_tune_save(const char *path)
+{
+    if (!path) return fail(CUBE_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(CUBE_EINVAL, "cannot write %s", path);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [");
+    bool first = true;
+    for (auto &kv : g_table) {
+        fprintf(f,
+                "%s\n  {\"kind\": %d, \"bins_log2\": %d, \"size_log2\": %d, \"threads\": %d, "
+                "\"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, \"ms\": %.5f}",
+                first ? "" : ",", kv.first.kind, kv.first.bins_log2, kv.first.size_log2,
+                kv.second.threads, kv.second.unroll, kv.second.copies, kv.second.blocks_per_cu,
+                kv.second.ms);
+        first = false;
+    }
+    fprintf(f, "\n]}\n");
+    fclose(f);
+    return CUBE_OK;
+}
+
+// Minimal reader for the format cube_tune_save writes: one entry per line.
+int cube_tune_load(const char *path)
+{
+    if (!path) return fail(CUBE_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(CUBE_EINVAL, "cannot read %s", path);
+    char line[512];
+    int n = 0;
+    bool arch_ok = false;
+    std::map<TuneKey, TunedShape> t;
+    while (fgets(line, sizeof line, f)) {
+        if (strstr(line, "\"arch\": \"gfx950\"")) arch_ok = true;
+        int kind, bl, sl, th, un, co, bp;
+        double ms;
+        if (sscanf(strchr(line, '{') ? strchr(line, '{') : line,
+                   "{\"kind\": %d, \"bins_log2\": %d, \"size_log2\": %d, \"threads\": %d, "
+                   "\"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, \"ms\": %lf}",
+                   &kind, &bl, &sl, &th, &un, &co, &bp, &ms) == 8) {
+            if ((th != 256 && th != 512 && th != 1024) || (un != 2 && un != 4) ||
+                co < 0 || co > 32 || (co & (co - 1)) || bp < 1 || bp > 64) {
+                fclose(f);
+                return fail(CUBE_EINVAL, "%s: bad entry", path);
+            }
+            TunedShape sh;
+            sh.threads = th;
+            sh.unroll = un;
+            sh.copies = co;
+            sh.blocks_per_cu = bp;
+            sh.ms = (float)ms;
+            t[TuneKey{kind, bl, sl}] = sh;
+            ++n;
+        }
+    }
+    fclose(f);
+    if (!arch_ok) return fail(CUBE_EINVAL, "%s: not a gfx950 tuning table", path);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &kv : t) g_table[kv.first] = kv.second;
+    return n;
+}
+
+void cube_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_table.clear();
+}
+
+}  // extern "C"

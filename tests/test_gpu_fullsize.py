@@ -1,0 +1,97 @@
+"""Full-size parity (GPU, slow): the 16 GiB brick against the oracle over the
+whole cube, in the launch configuration the benchmark times; and the
+precision-stress recipe (offset 1e4, noise 1e-3, sources up to 1e3) at 16 GiB,
+where the FP32-only accumulation modes are reported beside the production
+FP64-merge path.
+
+The oracle runs single-threaded on host copies; these tests take a minute or
+two each and are marked `slow` as well as `gpu`.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import assert_counts_match, assert_stats_match, rel_err
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import paper_1111_6661_amd as cs
+    assert torch.cuda.is_available()
+    cs.load()
+    cs.cube_set_launch(0, 0, 0, 0)
+    cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    return cs
+
+
+def _host_copy(t):
+    h = np.empty(tuple(t.shape), dtype=np.float32)
+    step = 64
+    for z in range(0, t.shape[0], step):
+        h[z:z + step] = t[z:z + step].cpu().numpy()
+    return h
+
+
+@pytest.mark.timeout(600)
+def test_brick16g_full_cube(cs):
+    import synth
+    name = "brick16g"
+    r = synth.WORKLOADS[name]
+    nb = synth.HIST_BINS[name]
+    t = synth.cube_tensor(r, synth.BASE_SEED + 1, device="cuda")
+    st_fused_ref = cs.stats(t)
+    st, counts = cs.stats_hist(t, st_fused_ref.min, st_fused_ref.max, nb)
+    st2, counts2 = cs.stats_hist_minmax(t, nb)
+    t0 = time.perf_counter()
+    host = _host_copy(t)
+    del t
+    torch.cuda.empty_cache()
+    ref = oracle.stats(host)
+    want = oracle.hist(host, ref.min, ref.max, nb)
+    print(f"oracle over 2^32 voxels: {time.perf_counter() - t0:.1f} s")
+    for got, what in ((st, "fused"), (st2, "two-pass"), (st_fused_ref, "stats")):
+        assert_stats_match(got, ref, what)
+        print(what, "rel err (mean, std):", rel_err(got, ref))
+    assert_counts_match(counts, want, "fused counts")
+    assert_counts_match(counts2, want, "two-pass counts")
+    assert int(want.sum()) == r.n
+
+
+@pytest.mark.timeout(600)
+def test_precision_stress_16g(cs):
+    import synth
+    base = synth.WORKLOADS["stress128g"]
+    r = base.scaled(2048, 2048, 1024)
+    t = synth.cube_tensor(r, synth.BASE_SEED + 4, device="cuda")
+    errs = {}
+    got = {}
+    try:
+        for mode, name in ((cs.CUBE_ACCUM_NAIVE32, "naive32"), (cs.CUBE_ACCUM_KAHAN32, "kahan32"),
+                           (cs.CUBE_ACCUM_FP64MERGE, "fp64merge")):
+            cs.cube_set_accum_mode(mode)
+            got[name] = cs.stats(t)
+    finally:
+        cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    host = _host_copy(t)
+    del t
+    torch.cuda.empty_cache()
+    ref = oracle.stats(host)
+    for name, st in got.items():
+        errs[name] = rel_err(st, ref)
+        assert st.n_valid == ref.n_valid and st.min == ref.min and st.max == ref.max
+    print("precision stress (mean err, std err):", errs)
+    assert_stats_match(got["fp64merge"], ref, "fp64merge")
+    assert errs["naive32"][1] > errs["fp64merge"][1]
+    out = os.environ.get("CUBE_PRECISION_REPORT")
+    if out:
+        import json
+        with open(out, "w") as f:
+            json.dump({"recipe": "stress128g scaled to 2048x2048x1024", "oracle_std": ref.std,
+                       "oracle_mean": ref.mean,
+                       "rel_err_mean_std": {k: list(v) for k, v in errs.items()}}, f, indent=1)

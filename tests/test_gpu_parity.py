@@ -180,8 +180,8 @@ def test_large_bin_counts(cs, tiny, nbins):
 
 
 @pytest.mark.parametrize("threads,blocks,copies,unroll", [
-    (256, 0, 0, 0), (512, 0, 1, 2), (1024, 0, 32, 8), (256, 1, 4, 4), (512, 7, 2, 8),
-    (1024, 300, 8, 2), (256, 4096, 16, 4), (256, 3, 1, 8),
+    (256, 0, 0, 0), (512, 0, 1, 2), (1024, 0, 32, 4), (256, 1, 4, 4), (512, 7, 2, 2),
+    (1024, 300, 8, 2), (256, 4096, 16, 4), (256, 3, 1, 2),
 ])
 def test_launch_shapes_agree(cs, tiny, threads, blocks, copies, unroll):
     t, host = tiny
