@@ -57,6 +57,37 @@ def time_launches(fn, stream, steps: int, warmup: int):
     return wall, ev
 
 
+KERNEL_SOURCES = ("paper_1111_6661_amd/csrc/cube_device.h",
+                  "paper_1111_6661_amd/csrc/cube_kernels.hip")
+PROFILE_SUMMARY = "profiles/fused_brick16g_trace_and_bytes.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per fused launch (FETCH + WRITE, scaled by the copy
+    calibration) from the committed rocprofv3 summary -- only if it was taken
+    on the current kernel sources, else None."""
+    path = os.path.join(ROOT, PROFILE_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    want = kernel_source_hash()
+    if f"kernel sources sha256[:16]: {want}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":", 1)[1])
+    return None
+
+
 def cpu_baseline(cube, nbins: int, lo: float, hi: float, target_s: float):
     """The oracle on the first planes of the cube, sized to about target_s."""
     import oracle
@@ -136,6 +167,46 @@ def bench_batch64(cs, synth, torch, dev, steps: int):
             "batched_voxels_per_s": nvox / (ev_b * 1e-3), "plain_voxels_per_s": nvox / (ev_p * 1e-3),
             "speedup": ev_p / ev_b, "counts_and_extrema_equal": counts_equal,
             "max_std_rel_diff_batched_vs_plain": worst}
+
+
+def bench_stress(cs, synth, torch, dev, steps: int):
+    """The precision-stress cube at full size (4096 x 4096 x 2048, 128 GiB,
+    offset 1e4): fused pass throughput over [min, max] with 4096 bins, and
+    the moments of the three accumulation modes side by side (the oracle
+    comparison of these modes runs in the test suite at 16 GiB)."""
+    name = "stress128g"
+    r = synth.WORKLOADS[name]
+    nb = synth.HIST_BINS[name]
+    log(f"stress: generating {r.nx}x{r.ny}x{r.nz} ({r.n * 4 / 2**30:.0f} GiB)")
+    cube = synth.cube_tensor(r, synth.BASE_SEED + 4, device=dev)
+    ptr, dims = cs.box_of(cube)
+    modes = {}
+    for mode, label in ((cs.CUBE_ACCUM_NAIVE32, "naive32"), (cs.CUBE_ACCUM_KAHAN32, "kahan32"),
+                        (cs.CUBE_ACCUM_FP64MERGE, "fp64merge")):
+        cs.cube_set_accum_mode(mode)
+        st = cs.stats(cube)
+        modes[label] = {"mean": st.mean, "std": st.std}
+    cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    st = cs.stats(cube)
+    stream = torch.cuda.Stream(device=dev)
+    sp = stream.cuda_stream
+    out = torch.zeros(64, dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(nb + 3, dtype=torch.int64, device=dev)
+    lo, hi = st.min, st.max
+    _, ms = time_launches(lambda: cs.cube_stats_hist_async(ptr, dims, lo, hi, nb, out.data_ptr(),
+                                                           cnt.data_ptr(), sp),
+                          stream, steps, 2)
+    c = cnt.cpu().numpy()
+    ref = modes["fp64merge"]
+    del cube
+    torch.cuda.empty_cache()
+    return {"voxels": r.n, "nbins": nb, "fused_ms": ms, "voxels_per_s": r.n / (ms * 1e-3),
+            "pct_hbm_peak": 100.0 * 4 * r.n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bin0_fraction_of_valid": float(c[0]) / max(1, st.n_valid),
+            "counts_sum_equals_n_total": int(c.sum()) == r.n,
+            "mean_std_by_mode": modes,
+            "std_rel_diff_vs_fp64merge": {k: abs(v["std"] - ref["std"]) / ref["std"]
+                                          for k, v in modes.items()}}
 
 
 def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7):
@@ -235,6 +306,7 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-item batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-stress", action="store_true", help="skip the 128 GiB stress cube")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -348,7 +420,10 @@ def main() -> int:
                                f"histogram over [min, max]",
                    "nbins": nbins, "voxels": r.n},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(),
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "kernel_sources": kernel_source_hash()},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "kernel_ms_events": ev_ms,
         "parity": parity,
@@ -359,8 +434,15 @@ def main() -> int:
         cb = cpu_baseline(cube, nbins, lo, hi, args.cpu_seconds)
         result["cpu_baseline"] = cb
         log(f"cpu baseline: {cb['value']:.3g} voxels/s")
-    if not args.only_fused and not args.no_serve:
+    if not args.only_fused and not args.no_stress:
         del cube
+        cube = None
+        torch.cuda.empty_cache()
+        extra["stress128g"] = bench_stress(cs, synth, torch, dev, 10)
+        log(f"stress128g: fused {extra['stress128g']['fused_ms']:.3f} ms "
+            f"({extra['stress128g']['pct_hbm_peak']:.1f} % of HBM peak)")
+    if not args.only_fused and not args.no_serve:
+        cube = None
         torch.cuda.empty_cache()
         sv = bench_serve(cs, synth, torch, dev, args.serve_seconds)
         extra["serve"] = sv

@@ -178,6 +178,21 @@ CUBE_API int cube_set_accum_mode(int32_t mode);
 CUBE_API int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll);
 
 /*
+ * Exact selection and median (Section 3 names the median as a global,
+ * multi-pass task).  cube_select stores in *value the valid voxel of rank
+ * `rank` (0-based) in the order by value with -0 before +0; CUBE_EINVAL if
+ * rank >= n_valid.  cube_median stores the median of the valid voxels: the
+ * middle one for odd n_valid, the FP64 mean of the two middle ones for even
+ * n_valid (and n_valid in *n_valid when not NULL); CUBE_EINVAL when no voxel
+ * is valid.  Three histogram passes over 32-bit order keys (12 + 12 + 8
+ * bits) per selected rank, with the bucket choice made on the device;
+ * synchronous, on the default stream; results are exact.
+ */
+CUBE_API int cube_select(const float *ptr, const int64_t *dims, uint64_t rank, float *value);
+CUBE_API int cube_median(const float *ptr, const int64_t *dims, double *median,
+                         uint64_t *n_valid);
+
+/*
  * Autotuner.  Times candidate launch shapes (threads, float4 loads per tile,
  * LDS histogram copies, blocks per CU) of one pass kind -- CUBE_Q_STATS,
  * CUBE_Q_HIST or CUBE_Q_FUSED over [lo, hi] -- on the given DEVICE box
@@ -239,6 +254,17 @@ CUBE_API int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t t
  * single-box call, except for the rounding of mean and m2 (the tiling
  * differs); counts and extrema are bit-exact. */
 CUBE_API int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *stream);
+/* Order of the queries' tiles in the work list: largest queries first (the
+ * default; shortest batch) or smallest first (lowest latency for small
+ * queries, whose completion is visible as soon as their tiles are done). */
+#define CUBE_ORDER_LARGEST_FIRST 0
+#define CUBE_ORDER_SMALLEST_FIRST 1
+CUBE_API int cube_batch_set_order(cube_batch_t *b, int32_t order);
+/* 1 when query i of the last launch of b has completed (its device outputs
+ * are final), else 0; reads a host-mapped flag that the kernel writes, with
+ * no GPU call.  Valid after cube_batch_enqueue and cube_batch_relaunch (a
+ * graph replay repeats the generation it captured, so use the stream). */
+CUBE_API int cube_batch_query_done(cube_batch_t *b, int32_t i);
 /* Launch the last enqueued work list again (no host work, no copies). */
 CUBE_API int cube_batch_relaunch(cube_batch_t *b, void *stream);
 /* Same as cube_batch_relaunch through a captured HIP graph: the first call

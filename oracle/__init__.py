@@ -100,6 +100,11 @@ class Oracle:
         lib.oracle_hist.restype = C.c_int
         lib.oracle_hist_accumulate.argtypes = lib.oracle_hist.argtypes
         lib.oracle_hist_accumulate.restype = C.c_int
+        lib.oracle_select.argtypes = [P, i64, i64, i64, i64, i64, C.c_uint64, C.POINTER(f32)]
+        lib.oracle_select.restype = C.c_int
+        lib.oracle_median.argtypes = [P, i64, i64, i64, i64, i64, C.POINTER(f64),
+                                      C.POINTER(C.c_uint64)]
+        lib.oracle_median.restype = C.c_int
         self.lib = lib
         self.path = path
 
@@ -131,6 +136,21 @@ class Oracle:
                 raise ValueError("invalid box")
         lib.oracle_finish(C.byref(s1), C.byref(s2), C.byref(out))
         return Stats(*(getattr(out, f[0]) for f in _Stats._fields_))
+
+    def select(self, a: np.ndarray, k: int) -> float:
+        """The valid voxel of rank k (0-based; -0 orders before +0)."""
+        v = C.c_float()
+        rc = self.lib.oracle_select(*box_of(a), k, C.byref(v))
+        if rc != 0:
+            raise ValueError("invalid box or rank")
+        return v.value
+
+    def median(self, a: np.ndarray) -> float:
+        """Median of the valid voxels (mean of the two middle ones if even)."""
+        m, n = C.c_double(), C.c_uint64()
+        if self.lib.oracle_median(*box_of(a), C.byref(m), C.byref(n)) != 0:
+            raise ValueError("no valid voxel or invalid box")
+        return m.value
 
     def hist_scale(self, lo: float, hi: float, nbins: int) -> float:
         """The FP32 scale nbins / (hi - lo); ValueError on an invalid range."""
@@ -193,6 +213,14 @@ def hist(a, lo, hi, nbins):
 
 def hist_pieces(pieces, lo, hi, nbins):
     return default().hist_pieces(pieces, lo, hi, nbins)
+
+
+def select(a, k):
+    return default().select(a, k)
+
+
+def median(a):
+    return default().median(a)
 
 
 def box_of(a: np.ndarray):

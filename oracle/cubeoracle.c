@@ -23,6 +23,11 @@
  *   std          : sqrt(m2 / n_valid)   (population standard deviation)
  *   mean_abs     : (1/n_valid) * sum |x|  (only used to scale tolerances)
  *
+ *   select(k)    : the valid voxel of rank k (0-based) in the order by value
+ *                  with -0 before +0; median = select((n-1)/2) for odd
+ *                  n_valid, the FP64 mean of select(n/2-1) and select(n/2)
+ *                  for even n_valid (the median task of Section 3).
+ *
  *   histogram over a closed range [lo, hi] with nbins bins, decided in FP32:
  *      blank            -> the NaN counter
  *      x < lo           -> the "below" counter
@@ -50,6 +55,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #if defined(__FAST_MATH__)
@@ -270,4 +276,61 @@ int oracle_hist(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t sy,
     if (nbins < 1 || nbins > 65536) return -1;
     memset(counts, 0, sizeof(uint64_t) * (size_t)(nbins + 3));
     return oracle_hist_accumulate(p, nx, ny, nz, sy, sz, lo, hi, nbins, counts);
+}
+
+/* qsort comparator for the total order of valid voxels: by value, -0 < +0. */
+static int cmp_float(const void *a, const void *b)
+{
+    float x = *(const float *)a, y = *(const float *)b;
+    if (before(x, y)) return -1;
+    if (before(y, x)) return 1;
+    return 0;
+}
+
+/*
+ * The valid voxel of rank k (0-based) of one box, by sorting every valid
+ * voxel.  Returns 0, or -1 for an invalid box or k >= n_valid, or -2 when
+ * the copy cannot be allocated.
+ */
+int oracle_select(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t sy,
+                  int64_t sz, uint64_t k, float *value)
+{
+    if (!dims_ok(nx, ny, nz, sy, sz)) return -1;
+    uint64_t n = 0, cap = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
+    float *v = (float *)malloc((cap ? cap : 1) * sizeof(float));
+    if (!v) return -2;
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                float f = p[x + sy * y + sz * z];
+                if (f == f) v[n++] = f;
+            }
+    if (k >= n) {
+        free(v);
+        return -1;
+    }
+    qsort(v, (size_t)n, sizeof(float), cmp_float);
+    *value = v[k];
+    free(v);
+    return 0;
+}
+
+/* Median of the valid voxels (see the header); -1 when there is none. */
+int oracle_median(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t sy,
+                  int64_t sz, double *median, uint64_t *n_valid)
+{
+    oracle_stats_t st;
+    if (oracle_stats(p, nx, ny, nz, sy, sz, &st)) return -1;
+    *n_valid = st.n_valid;
+    if (st.n_valid == 0) return -1;
+    float a, b;
+    if (st.n_valid % 2 == 1) {
+        if (oracle_select(p, nx, ny, nz, sy, sz, (st.n_valid - 1) / 2, &a)) return -1;
+        *median = (double)a;
+    } else {
+        if (oracle_select(p, nx, ny, nz, sy, sz, st.n_valid / 2 - 1, &a)) return -1;
+        if (oracle_select(p, nx, ny, nz, sy, sz, st.n_valid / 2, &b)) return -1;
+        *median = ((double)a + (double)b) / 2.0;
+    }
+    return 0;
 }

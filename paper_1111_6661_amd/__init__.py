@@ -46,6 +46,7 @@ class cube_stats_t(C.Structure):
 assert C.sizeof(cube_stats_t) == 64
 
 CUBE_Q_STATS, CUBE_Q_HIST, CUBE_Q_FUSED, CUBE_Q_MINMAX = 0, 1, 2, 3
+CUBE_ORDER_LARGEST_FIRST, CUBE_ORDER_SMALLEST_FIRST = 0, 1
 
 
 class cube_query_t(C.Structure):
@@ -108,6 +109,8 @@ def load() -> C.CDLL:
     lib.cube_batch_set_tile.argtypes = [P, i64, i32]
     lib.cube_batch_enqueue.argtypes = [P, C.POINTER(cube_query_t), i32, P]
     lib.cube_batch_relaunch.argtypes = [P, P]
+    lib.cube_batch_set_order.argtypes = [P, i32]
+    lib.cube_batch_query_done.argtypes = [P, i32]
     lib.cube_batch_graph_launch.argtypes = [P, P]
     lib.cube_batch_check.argtypes = [P]
     lib.cube_batch_run.argtypes = [C.POINTER(cube_query_t), i32]
@@ -116,6 +119,10 @@ def load() -> C.CDLL:
     lib.cube_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_double)]
     lib.cube_server_latency.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_uint64), i32]
+    lib.cube_select.argtypes = [P, I64P, C.c_uint64, C.POINTER(C.c_float)]
+    lib.cube_select.restype = C.c_int
+    lib.cube_median.argtypes = [P, I64P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    lib.cube_median.restype = C.c_int
     lib.cube_autotune.argtypes = [P, I64P, i32, f32, f32, i32, i32, C.c_char_p, C.c_size_t]
     lib.cube_autotune.restype = C.c_int
     lib.cube_tune_save.argtypes = [C.c_char_p]
@@ -129,6 +136,7 @@ def load() -> C.CDLL:
                  "cube_server_latency"):
         getattr(lib, name).restype = C.c_int
     for name in ("cube_batch_create", "cube_batch_set_tile", "cube_batch_enqueue",
+                 "cube_batch_set_order", "cube_batch_query_done",
                  "cube_batch_relaunch", "cube_batch_graph_launch", "cube_batch_check",
                  "cube_batch_run"):
         getattr(lib, name).restype = C.c_int
@@ -219,6 +227,29 @@ def cube_set_accum_mode(mode: int) -> int:
 def cube_set_launch(threads: int = 0, blocks: int = 0, hist_copies: int = 0,
                     unroll: int = 0) -> None:
     _check(load().cube_set_launch(threads, blocks, hist_copies, unroll))
+
+
+def cube_select(ptr: int, dims, rank: int) -> float:
+    v = C.c_float()
+    _check(load().cube_select(C.c_void_p(ptr), _dims(dims), rank, C.byref(v)))
+    return v.value
+
+
+def cube_median(ptr: int, dims):
+    """(median, n_valid) of a device box."""
+    m, n = C.c_double(), C.c_uint64()
+    _check(load().cube_median(C.c_void_p(ptr), _dims(dims), C.byref(m), C.byref(n)))
+    return m.value, n.value
+
+
+def select(t, rank: int) -> float:
+    ptr, d = box_of(t)
+    return cube_select(ptr, d, rank)
+
+
+def median(t):
+    ptr, d = box_of(t)
+    return cube_median(ptr, d)
 
 
 def cube_autotune(ptr: int, dims, kind: int, lo: float = 0.0, hi: float = 0.0, nbins: int = 1,
@@ -317,6 +348,12 @@ class Batch:
         arr = (cube_query_t * len(queries))(*queries)
         self._keep = arr
         _check(load().cube_batch_enqueue(self._h, arr, len(queries), C.c_void_p(stream)))
+
+    def set_order(self, order: int) -> None:
+        _check(load().cube_batch_set_order(self._h, order))
+
+    def query_done(self, i: int) -> bool:
+        return bool(load().cube_batch_query_done(self._h, i))
 
     def relaunch(self, stream: int = 0) -> None:
         _check(load().cube_batch_relaunch(self._h, C.c_void_p(stream)))

@@ -66,6 +66,8 @@ struct BatchArgs {
     unsigned int *ctl;             // [0] next tile, [1] exit ticket, [2] error flag
     int32_t accum_mode;
     unsigned int spin_limit;
+    unsigned int *done_flags;      // host-mapped, one per query: `gen` once done
+    unsigned int gen;
 };
 
 constexpr int BATCH_UNROLL = 4;
@@ -146,11 +148,12 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
             write_wave_record<false, CUBE_ACCUM_FP64MERGE>(L, W, &recs[(long long)tile.local * nw + wid]);
         if (hist) hist_flush(lds, it.nbins, a.copies_log2, acc);
 
-        // Completion of the query's phase: the last tile merges.
-        __threadfence();
+        // Completion of the query's phase: the last tile merges.  One
+        // release fence per block, after the barrier (see k_pass).
         __syncthreads();
         const int ntiles = tile.phase == 1 ? it.ntiles1 : it.ntiles2;
         if (tid == 0) {
+            __threadfence();
             unsigned int *done = tile.phase == 1 ? &st->done1 : &st->done2;
             s_flag = atomicAdd(done, 1u) == (unsigned int)(ntiles - 1);
         }
@@ -173,10 +176,13 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
             if (hist)
                 finish_hist(acc, it.counts, it.nbins, hist_on, below, above,
                             it.g.n_total - nv);
+            __syncthreads();
             if (tid == 0) {
+                bool finished = true;
                 if (tile.phase == 1) {
                     st->done1 = 0u;
                     if (it.kind == BQ_MINMAX) {
+                        finished = false;
                         __threadfence();
                         __hip_atomic_store(&st->ready, 1u, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
@@ -187,13 +193,18 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                     st->done2 = 0u;
                     st->ready = 0u;
                 }
+                if (finished && a.done_flags) {
+                    // The query's outputs are complete: tell the host.
+                    __threadfence_system();
+                    __hip_atomic_store(&a.done_flags[tile.item], a.gen, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                }
             }
         }
         __syncthreads();
     }
 
     // The last block to leave returns the work counters to zero.
-    __threadfence();
     if (tid == 0 && atomicAdd(&a.ctl[1], 1u) == gridDim.x - 1) {
         a.ctl[0] = 0u;
         a.ctl[1] = 0u;
@@ -232,6 +243,11 @@ struct cube_batch {
     BatchTile *h_tiles = nullptr;   // pinned
     hipStream_t last_stream = nullptr;
     hipEvent_t staged = nullptr;    // the last work-list copy has been read
+    unsigned int *h_done = nullptr; // host-mapped per-query completion flags
+    unsigned int *d_done = nullptr; // the same memory as the device sees it
+    size_t cap_done = 0;
+    unsigned int gen = 0;
+    int order = 0;                  // 0 largest queries first, 1 smallest first
     bool have_work = false;
     BatchArgs args;
     int threads = 512, blocks = 0;
@@ -316,8 +332,32 @@ int ensure(cube_batch *b, size_t items, size_t tiles, size_t recs, size_t acc)
     return CUBE_OK;
 }
 
+// Host-mapped completion flags for `n` queries (kept, grown on demand).
+int ensure_done(cube_batch *b, size_t n)
+{
+    if (n <= b->cap_done) return CUBE_OK;
+    if (b->have_work) hipStreamSynchronize(b->last_stream);
+    if (b->h_done) hipHostFree(b->h_done);
+    b->h_done = nullptr;
+    b->d_done = nullptr;
+    b->cap_done = 0;
+    const size_t cap = n < 256 ? 256 : n * 2;
+    hipError_t e;
+    if ((e = hipHostMalloc(&b->h_done, cap * 4, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
+        return hip_fail(e, "completion flags");
+    memset(b->h_done, 0, cap * 4);
+    if ((e = hipHostGetDevicePointer((void **)&b->d_done, b->h_done, 0)) != hipSuccess)
+        return hip_fail(e, "completion flags (device view)");
+    b->cap_done = cap;
+    return CUBE_OK;
+}
+
 int launch_batch(cube_batch *b, hipStream_t s)
 {
+    // A new generation per launch: completion flags of earlier launches
+    // never read as done.
+    if (++b->gen == 0) ++b->gen;
+    b->args.gen = b->gen;
     BatchArgs a = b->args;
     void *args[] = {&a};
     hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&k_batch), dim3(b->blocks),
@@ -348,6 +388,7 @@ void cube_batch_destroy(cube_batch_t *b)
         drop_graph(b);
         free_buffers(b);
         if (b->staged) hipEventDestroy(b->staged);
+        if (b->h_done) hipHostFree(b->h_done);
     }
     delete b;
 }
@@ -438,8 +479,13 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     // the same order.
     std::vector<long long> sz((size_t)n);
     for (int i = 0; i < n; ++i) sz[(size_t)i] = items[(size_t)i].ntiles1;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](long long x, long long y) { return sz[(size_t)x] > sz[(size_t)y]; });
+    if (b->order == 0)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](long long x, long long y) { return sz[(size_t)x] > sz[(size_t)y]; });
+    else
+        std::stable_sort(order.begin(), order.end(),
+                         [&](long long x, long long y) { return sz[(size_t)x] < sz[(size_t)y]; });
+    if ((rc = ensure_done(b, (size_t)n))) return rc;
     // A launch still running on another stream reads the device work list:
     // wait for it.  On the same stream, stream order protects the device
     // buffers; the pinned staging must still have been read by the previous
@@ -496,9 +542,26 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     a.ctl = b->d_ctl;
     a.accum_mode = CUBE_ACCUM_FP64MERGE;
     a.spin_limit = 1u << 24;
+    a.done_flags = b->d_done;
     b->have_work = n > 0;
     if (!b->have_work) return CUBE_OK;
     return launch_batch(b, s);
+}
+
+int cube_batch_set_order(cube_batch_t *b, int32_t order)
+{
+    if (!b) return fail(CUBE_EINVAL, "batch is NULL");
+    if (order != CUBE_ORDER_LARGEST_FIRST && order != CUBE_ORDER_SMALLEST_FIRST)
+        return fail(CUBE_EINVAL, "unknown order %d", order);
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->order = order == CUBE_ORDER_SMALLEST_FIRST ? 1 : 0;
+    return CUBE_OK;
+}
+
+int cube_batch_query_done(cube_batch_t *b, int32_t i)
+{
+    if (!b || i < 0 || (size_t)i >= b->cap_done || !b->h_done) return 0;
+    return __atomic_load_n(&b->h_done[i], __ATOMIC_ACQUIRE) == b->args.gen ? 1 : 0;
 }
 
 int cube_batch_relaunch(cube_batch_t *b, void *stream)

@@ -443,9 +443,12 @@ __device__ __forceinline__ void hist_flush(const unsigned int *lds, int nbins, i
 {
     __syncthreads();
     const int C = 1 << copies_log2;
+    // Each thread starts at its own copy (c + tid) so that the threads of a
+    // wavefront read different banks at every step.
+    const int rot = threadIdx.x;
     for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
         unsigned int sum = 0;
-        for (int c = 0; c < C; ++c) sum += lds[((b + 1) << copies_log2) + c];
+        for (int c = 0; c < C; ++c) sum += lds[((b + 1) << copies_log2) + ((c + rot) & (C - 1))];
         if (b == nbins - 1)  // floor(u) == nbins belongs to the last bin
             for (int c = 0; c < C; ++c) sum += lds[((nbins + 1) << copies_log2) + c];
         if (sum) atomicAdd(&acc[b], (unsigned long long)sum);

@@ -1,0 +1,359 @@
+// cube_select.hip -- exact selection (k-th smallest valid voxel) and the
+// median by histogram refinement: the global, multi-pass median task the
+// paper names in Section 3.
+//
+// Every valid voxel maps to a 32-bit key that orders like the value (-0
+// before +0): key = bits ^ (sign ? 0xffffffff : 0x80000000).  Three passes
+// histogram the key 12, 12 and 8 bits at a time; in each pass only voxels
+// whose key starts with the prefix chosen so far are counted.  The last
+// block of a pass scans that pass's histogram, picks the bin holding the
+// wanted rank, extends the prefix and lowers the rank, on the device, so the
+// host never waits between passes.  After the third pass the prefix is the
+// whole key of the selected voxel.  Counting uses the same lane-interleaved
+// LDS sub-histograms as the statistics pass, flushed with one 64-bit atomic
+// per non-empty bin per block.
+#include <string.h>
+
+#include <mutex>
+
+#include "cube_device.h"
+
+namespace cube {
+
+struct SelectState {
+    unsigned long long rank;     // rank still wanted inside the prefix bucket
+    unsigned long long n_valid;  // valid voxels (set by the first pass)
+    unsigned int prefix;         // key bits chosen so far
+    unsigned int error;          // 1: rank >= n_valid
+    float value;                 // the selected voxel (after the last pass)
+    unsigned int rank_mode;      // 0: `rank` as given; 1: (n_valid - 1) / 2;
+                                 // 2: n_valid / 2 (set once n_valid is known)
+};
+
+struct SelectArgs {
+    Geom g;
+    int32_t pass, copies_log2;
+    SelectState *st;
+    unsigned long long *acc;     // 4096 accumulators, zero between passes
+    unsigned int *ticket;
+    float *out;                  // optional device copy of the result
+};
+
+// Pass p histograms key bits [shift, shift + width): widths 12, 12, 8.
+__host__ __device__ __forceinline__ int sel_width(int p) { return p == 2 ? 8 : 12; }
+__host__ __device__ __forceinline__ int sel_shift(int p) { return p == 0 ? 20 : (p == 1 ? 8 : 0); }
+constexpr int SEL_U = 4;
+
+__device__ __forceinline__ unsigned int order_key(float x)
+{
+    const unsigned int u = __float_as_uint(x);
+    return u ^ ((unsigned int)((int)u >> 31) | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_value(unsigned int k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+struct SelCtx {
+    unsigned int prefix_hi;  // the chosen prefix in place (key bits above the bins)
+    unsigned int hi_mask;    // the bits it covers (0 in the first pass)
+    int bin_shift;
+    unsigned int bin_mask;
+    int shift, base;    // LDS addressing as in Hist
+    unsigned int *lds;
+};
+
+template <int NV>
+__device__ __forceinline__ void select_step(const float (&x)[NV], unsigned long long &valid,
+                                            const SelCtx &c)
+{
+    unsigned int cv = 0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const float v = x[j];
+        const unsigned long long mv = __builtin_amdgcn_ballot_w64(v == v);
+        cv += __popcll(mv);
+        const unsigned int k = order_key(v);
+        const bool match = ((k ^ c.prefix_hi) & c.hi_mask) == 0u;
+        const unsigned long long inr = mv & __builtin_amdgcn_ballot_w64(match);
+        const int b = (int)((k >> c.bin_shift) & c.bin_mask);
+        const int bb = keep_or_minus1(b, inr);
+        atomicAdd((unsigned int *)((char *)c.lds + ((bb << c.shift) + c.base)), 1u);
+    }
+    asm("" : "+s"(cv));
+    valid += cv;
+}
+
+__global__ void __launch_bounds__(1024) k_select(SelectArgs a)
+{
+    extern __shared__ unsigned int lds[];
+    __shared__ unsigned int s_last;
+    __shared__ unsigned long long s_part[1024];
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int p = a.pass;
+    const int width = sel_width(p);
+    const int nbins = 1 << width;
+    SelCtx c;
+    const int top = sel_shift(p) + width;   // first key bit above this pass's bins
+    c.hi_mask = p == 0 ? 0u : (0xffffffffu << top);
+    c.prefix_hi = p == 0 ? 0u : (a.st->prefix << top);
+    c.bin_shift = sel_shift(p);
+    c.bin_mask = (unsigned int)nbins - 1u;
+    const int C = 1 << a.copies_log2;
+    c.shift = a.copies_log2 + 2;
+    c.base = (C + (tid & 63 & (C - 1))) * 4;
+    c.lds = lds;
+    lds_zero(lds, nbins, a.copies_log2);
+
+    unsigned long long valid = 0;
+    const Geom &g = a.g;
+    const unsigned long long G = gridDim.x;
+    const long long u0 = (long long)(((unsigned long long)g.n_units * blockIdx.x) / G);
+    const long long u1 = (long long)(((unsigned long long)g.n_units * (blockIdx.x + 1)) / G);
+    const int lane = tid & 63, wid = tid >> 6;
+    if (u0 < u1) {
+        long long row = u0 / g.segs;
+        long long s = u0 - row * g.segs;
+        long long y = row % g.ny;
+        long long z = row / g.ny;
+        for (long long u = u0; u < u1; ++u) {
+            const float *q = g.ptr + y * g.sy + z * g.sz + s * g.seg_len;
+            const long long c0 = s * g.seg_len;
+            const long long len = min(g.seg_len, g.row_len - c0);
+            const long long mis = (long long)((16 - ((uintptr_t)q & 15)) & 15) >> 2;
+            const long long h = min(len, mis);
+            const long long n4 = (len - h) >> 2;
+            const long long t = len - h - 4 * n4;
+            if (wid == 0 && h + t > 0) {
+                long long idx = lane < h ? lane : h + 4 * n4 + (lane - h);
+                const bool have = lane < h + t;
+                idx = have ? idx : 0;
+                const float v = q[idx];
+                float xv[1] = {have ? v : qnan()};
+                select_step<1>(xv, valid, c);
+            }
+            const f4 *q4 = (const f4 *)(q + h);
+            const long long T = (long long)B * SEL_U;
+            long long i0 = 0;
+            for (; i0 + T <= n4; i0 += T) {
+                f4 v[SEL_U];
+                load_tile<SEL_U>(v, q4, i0, B, tid);
+                float xv[4 * SEL_U];
+#pragma unroll
+                for (int k = 0; k < SEL_U; ++k) {
+                    xv[4 * k + 0] = v[k].x;
+                    xv[4 * k + 1] = v[k].y;
+                    xv[4 * k + 2] = v[k].z;
+                    xv[4 * k + 3] = v[k].w;
+                }
+                select_step<4 * SEL_U>(xv, valid, c);
+            }
+            for (; i0 < n4; i0 += B) {
+                const long long i = i0 + tid;
+                const bool have = i < n4;
+                const f4 v = __builtin_nontemporal_load(q4 + (have ? i : n4 - 1));
+                float xv[4] = {have ? v.x : qnan(), have ? v.y : qnan(), have ? v.z : qnan(),
+                               have ? v.w : qnan()};
+                select_step<4>(xv, valid, c);
+            }
+            if (++s == g.segs) {
+                s = 0;
+                if (++y == g.ny) {
+                    y = 0;
+                    ++z;
+                }
+            }
+        }
+    }
+    // Flush bins (slot b + 1 holds bin b); the valid count goes with the
+    // first pass.
+    __syncthreads();
+    for (int b = tid; b < nbins; b += B) {
+        unsigned int sum = 0;
+        for (int k = 0; k < C; ++k) sum += lds[((b + 1) << a.copies_log2) + k];
+        if (sum) atomicAdd(&a.acc[b], (unsigned long long)sum);
+    }
+    if (p == 0 && lane == 0 && valid) atomicAdd(&a.st->n_valid, valid);
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();  // one release per block, after the barrier
+        s_last = (atomicAdd(a.ticket, 1u) == (unsigned int)(gridDim.x - 1));
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+
+    // Last block: find the bin holding the rank (counts in bin order), then
+    // return the accumulators to zero.
+    const int per = (nbins + B - 1) / B;
+    unsigned long long mine = 0;
+    for (int k = 0; k < per; ++k) {
+        const int b = tid * per + k;
+        if (b < nbins) mine += a.acc[b];
+    }
+    s_part[tid] = mine;
+    __syncthreads();
+    if (tid == 0) {
+        SelectState st = *a.st;
+        if (p == 0 && st.rank_mode == 1 && st.n_valid) st.rank = (st.n_valid - 1) / 2;
+        if (p == 0 && st.rank_mode == 2) st.rank = st.n_valid / 2;
+        if (p == 0 && st.rank >= st.n_valid) st.error = 1u;
+        if (!st.error) {
+            unsigned long long before = 0;
+            int t = 0;
+            while (t < B - 1 && before + s_part[t] <= st.rank) before += s_part[t++];
+            int b = t * per;
+            while (b < nbins - 1 && before + a.acc[b] <= st.rank) before += a.acc[b++];
+            st.prefix = (st.prefix << width) | (unsigned int)b;
+            st.rank -= before;
+            if (p == 2) {
+                st.value = key_value(st.prefix);
+                if (a.out) *a.out = st.value;
+            }
+        }
+        *a.st = st;
+    }
+    __syncthreads();
+    for (int b = tid; b < nbins; b += B) a.acc[b] = 0ull;
+    if (tid == 0) *a.ticket = 0u;
+}
+
+}  // namespace cube
+
+using namespace cube;
+
+namespace {
+
+struct SelectWorkspace {
+    SelectState *st = nullptr;
+    unsigned long long *acc = nullptr;
+    unsigned int *ticket = nullptr;
+    SelectState *h_st = nullptr;  // pinned
+};
+
+std::mutex g_smu;
+SelectWorkspace g_sws[64];
+bool g_sws_ready[64];
+
+int select_ws(SelectWorkspace **out)
+{
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) return fail(CUBE_EINVAL, "device index out of range");
+    if (!g_sws_ready[dev]) {
+        SelectWorkspace &w = g_sws[dev];
+        hipError_t e;
+        if ((e = hipMalloc(&w.st, sizeof(SelectState))) != hipSuccess ||
+            (e = hipMalloc(&w.acc, 4096 * 8)) != hipSuccess ||
+            (e = hipMalloc(&w.ticket, 256)) != hipSuccess ||
+            (e = hipHostMalloc(&w.h_st, sizeof(SelectState))) != hipSuccess ||
+            (e = hipMemset(w.acc, 0, 4096 * 8)) != hipSuccess ||
+            (e = hipMemset(w.ticket, 0, 256)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            return hip_fail(e, "select workspace");
+        g_sws_ready[dev] = true;
+    }
+    *out = &g_sws[dev];
+    return CUBE_OK;
+}
+
+// Three passes on the default stream; the result is read back.  With
+// rank_mode 1 or 2 the rank is the lower / upper middle of the valid voxels.
+int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64_t *n_valid)
+{
+    SelectWorkspace *w = nullptr;
+    int rc = select_ws(&w);
+    if (rc) return rc;
+    SelectState init;
+    memset(&init, 0, sizeof init);
+    init.rank = rank;
+    init.rank_mode = (unsigned int)rank_mode;
+    hipError_t e;
+    // Synchronous copy: the workspace is reused by the next call.
+    if ((e = hipMemcpy(w->st, &init, sizeof init, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "select state");
+    SelectArgs a;
+    memset(&a, 0, sizeof a);
+    collapse(b, &a.g);
+    const int threads = 1024;
+    const int blocks = cu_count() * 2;
+    const long long rows = a.g.ny * a.g.nz;
+    long long segs = rows < blocks ? (blocks + rows - 1) / rows : 1;
+    long long seg_len = ((a.g.row_len + segs - 1) / segs + 3) & ~3LL;
+    if (seg_len < 4) seg_len = 4;
+    a.g.seg_len = seg_len;
+    a.g.segs = (a.g.row_len + seg_len - 1) / seg_len;
+    a.g.n_units = rows * a.g.segs;
+    a.st = w->st;
+    a.acc = w->acc;
+    a.ticket = w->ticket;
+    for (int p = 0; p < 3; ++p) {
+        a.pass = p;
+        const int nb = 1 << sel_width(p);
+        a.copies_log2 = nb >= 4096 ? 3 : 5;
+        const size_t lds = ((size_t)(nb + 2) << a.copies_log2) * 4;
+        const void *k = reinterpret_cast<const void *>(&k_select);
+        if (lds > 64 * 1024 &&
+            (e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+                hipSuccess)
+            return hip_fail(e, "select LDS");
+        SelectArgs ac = a;
+        void *args[] = {&ac};
+        if ((e = hipLaunchKernel(k, dim3((unsigned)blocks), dim3(threads), args, lds, nullptr)) !=
+            hipSuccess)
+            return hip_fail(e, "select launch");
+    }
+    if ((e = hipMemcpy(w->h_st, w->st, sizeof(SelectState), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "select result");
+    if (n_valid) *n_valid = w->h_st->n_valid;
+    if (w->h_st->error)
+        return fail(CUBE_EINVAL, "rank %llu >= %llu valid voxels", (unsigned long long)rank,
+                    (unsigned long long)w->h_st->n_valid);
+    *value = w->h_st->value;
+    return CUBE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cube_select(const float *ptr, const int64_t *dims, uint64_t rank, float *value)
+{
+    if (!value) return fail(CUBE_EINVAL, "value is NULL");
+    Box b;
+    int rc = check_box(ptr, dims, &b);
+    if (!rc) rc = check_box_device(&b);
+    if (rc) return rc;
+    if (b.n == 0) return fail(CUBE_EINVAL, "empty box");
+    std::lock_guard<std::mutex> lk(g_smu);
+    return select_rank(b, rank, 0, value, nullptr);
+}
+
+int cube_median(const float *ptr, const int64_t *dims, double *median, uint64_t *n_valid)
+{
+    if (!median) return fail(CUBE_EINVAL, "median is NULL");
+    Box b;
+    int rc = check_box(ptr, dims, &b);
+    if (!rc) rc = check_box_device(&b);
+    if (rc) return rc;
+    if (b.n == 0) return fail(CUBE_EINVAL, "empty box");
+    std::lock_guard<std::mutex> lk(g_smu);
+    // The lower middle (which is the median for odd n_valid), then for even
+    // n_valid the upper middle too.
+    float a = 0.f, c = 0.f;
+    uint64_t n = 0;
+    rc = select_rank(b, 0, 1, &a, &n);
+    if (n_valid) *n_valid = n;
+    if (n == 0) return fail(CUBE_EINVAL, "no valid voxel");
+    if (rc) return rc;
+    if (n % 2 == 1) {
+        *median = (double)a;
+    } else {
+        if ((rc = select_rank(b, 0, 2, &c, nullptr))) return rc;
+        *median = ((double)a + (double)c) / 2.0;
+    }
+    return CUBE_OK;
+}
+
+}  // extern "C"

@@ -328,7 +328,35 @@ def pin_hist_validation(o):
     assert o.hist_scale(f32(1.0), f32(1.0), 3) == 0.0
 
 
+# --------------------------------------------------------------- selection
+def pin_select(o):
+    rng = np.random.default_rng(8)
+    for n in (1, 2, 3, 10, 1001):
+        a = (rng.standard_normal(n) * 50).astype(np.float32)
+        if n > 3:
+            a[rng.random(n) < 0.1] = np.nan
+        valid = np.sort(a[~np.isnan(a)])          # numpy's sort as the reference
+        for k in sorted({0, len(valid) // 2, len(valid) - 1}):
+            assert o.select(a, k) == valid[k], (n, k)
+        med = np.median(valid.astype(np.float64))  # numpy's median as the reference
+        assert o.median(a) == med, (n, o.median(a), med)
+    # integer ramp: the median is (N-1)/2 exactly, select(k) = k
+    v = np.arange(1000, dtype=np.float32)[::-1].copy()
+    assert o.median(v) == 499.5 and o.select(v, 0) == 0.0 and o.select(v, 999) == 999.0
+    # signed zeros: -0 before +0; infinities are values; NaN is skipped
+    a = np.array([0.0, -0.0, np.nan, np.inf, -np.inf, 0.0], dtype=np.float32)
+    got = [o.select(a, k) for k in range(5)]
+    assert got[0] == -np.inf and got[4] == np.inf
+    assert signbit(got[1]) and not signbit(got[2]) and not signbit(got[3])
+    for bad in (5, 100):
+        try:
+            o.select(a, bad)
+        except ValueError:
+            continue
+        raise AssertionError("accepted an out-of-range rank")
+
+
 ALL_PINS = [pin_textbook, pin_exact_rational, pin_closed_forms, pin_merge,
             pin_extrema_nan, pin_strided, pin_hist_ramp, pin_hist_unit_scale,
             pin_hist_edges, pin_hist_subnormal, pin_hist_rounding_model, pin_hist_numpy,
-            pin_hist_invariants, pin_hist_validation]
+            pin_hist_invariants, pin_hist_validation, pin_select]

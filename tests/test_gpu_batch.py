@@ -142,3 +142,23 @@ def test_batch_validation(cs):
     cs.cube_batch_run([e])
     st = cs.Stats.from_bytes(out.cpu().numpy().tobytes())
     assert st.n_total == 0 and st.flags & cs.CUBE_NO_VALID
+
+
+def test_query_done_flags_and_order(cs):
+    items = make_items(seed=12, n=8)
+    outs = Outputs(len(items), 256)
+    qs = queries_for(cs, items, outs, [cs.CUBE_Q_MINMAX, cs.CUBE_Q_STATS], [256])
+    b = cs.Batch(tile_voxels=1 << 14)
+    b.set_order(cs.CUBE_ORDER_SMALLEST_FIRST)
+    b.enqueue(qs)
+    b.check()
+    assert all(b.query_done(i) for i in range(len(items)))
+    for i, t in enumerate(items):
+        check_query(cs, outs, i, t, [cs.CUBE_Q_MINMAX, cs.CUBE_Q_STATS][i % 2], 256)
+    b.relaunch()
+    b.check()
+    assert all(b.query_done(i) for i in range(len(items)))
+    assert not b.query_done(len(items) + 1000)
+    with pytest.raises(cs.CubeError):
+        b.set_order(7)
+    b.close()

@@ -1,0 +1,72 @@
+"""Exact selection and median (GPU) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import same_f32
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import paper_1111_6661_amd as cs
+    assert torch.cuda.is_available()
+    cs.load()
+    return cs
+
+
+def test_select_and_median_tiny(cs):
+    import synth
+    t = synth.cube_tensor(synth.WORKLOADS["tiny"], synth.BASE_SEED, device="cuda")
+    host = t.cpu().numpy()
+    ref = oracle.stats(host)
+    n = ref.n_valid
+    for k in (0, 1, n // 3, n // 2, n - 2, n - 1):
+        assert same_f32(cs.select(t, k), oracle.select(host, k)), k
+    m, nv = cs.median(t)
+    assert nv == n and m == oracle.median(host)
+    with pytest.raises(cs.CubeError):
+        cs.select(t, n)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 1, 1), (1001, 3, 1), (257, 129, 33)])
+def test_median_shapes(cs, shape):
+    import synth
+    r = synth.WORKLOADS["tiny"].scaled(*shape)
+    t = synth.cube_tensor(r, 55, device="cuda")
+    host = t.cpu().numpy()
+    if oracle.stats(host).n_valid == 0:
+        with pytest.raises(cs.CubeError):
+            cs.median(t)
+        return
+    m, _ = cs.median(t)
+    assert m == oracle.median(host)
+
+
+def test_select_special_values(cs):
+    a = np.array([0.0, -0.0, np.nan, np.inf, -np.inf, 0.0, 3.5, -1e-45, 1e-45, np.nan],
+                 dtype=np.float32)
+    t = torch.from_numpy(a).cuda()
+    n = int((~np.isnan(a)).sum())
+    for k in range(n):
+        assert same_f32(cs.select(t, k), oracle.select(a, k)), k
+    assert cs.median(t)[0] == oracle.median(a)
+    with pytest.raises(cs.CubeError):
+        cs.median(torch.full((10,), float("nan"), device="cuda"))
+
+
+def test_median_strided_and_ties(cs):
+    import synth
+    big = synth.cube_tensor(synth.WORKLOADS["tiny"].scaled(200, 50, 20), 8, device="cuda")
+    view = big[2:17, 3:44, 5:190]
+    host = big.cpu().numpy()[2:17, 3:44, 5:190]
+    assert cs.median(view)[0] == oracle.median(host)
+    # many ties: a cube of a few distinct values
+    a = np.repeat(np.array([1.0, 2.0, 2.0, 3.0], np.float32), 12345)
+    t = torch.from_numpy(a).cuda()
+    assert cs.median(t)[0] == 2.0
+    assert cs.select(t, 0) == 1.0 and cs.select(t, a.size - 1) == 3.0

@@ -42,6 +42,9 @@ MUTANTS = {
     "degenerate_range_rejected": ("if (width == 0.0f) {\n        *scale = 0.0f;\n        return 0;",
                                   "if (width == 0.0f) {\n        *scale = 0.0f;\n        return -1;"),
     "ftz_like_truncation": ("int64_t b = (int64_t)floorf(u);", "int64_t b = (int64_t)floorf(u + 1e-7f);"),
+    "select_includes_nan": ("if (f == f) v[n++] = f;", "v[n++] = f;"),
+    "select_reversed": ("if (before(x, y)) return -1;", "if (before(x, y)) return 1;"),
+    "median_upper_only": ("*median = ((double)a + (double)b) / 2.0;", "*median = (double)b;"),
 }
 
 
