@@ -60,6 +60,8 @@ def time_launches(fn, stream, steps: int, warmup: int):
 KERNEL_SOURCES = ("paper_1111_6661_amd/csrc/cube_device.h",
                   "paper_1111_6661_amd/csrc/cube_kernels.hip")
 PROFILE_SUMMARY = "profiles/fused_brick16g_trace_and_bytes.md"
+# Launch shapes the autotuner chose on an MI355X for the brick's pass kinds.
+TUNE_TABLE = "paper_1111_6661_amd/tuning/gfx950.json"
 
 
 def kernel_source_hash() -> str:
@@ -292,6 +294,35 @@ def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7):
             "results_equal_plain_vs_served": same_counts and same_extrema}
 
 
+def bench_select(cs, torch, cube, n_valid: int, reps: int):
+    """Exact selection of the lower middle and the median of the brick.
+
+    Each selection reads the cube three times (three 4 B/voxel passes); the
+    calls are synchronous, so the times include their small host copies.  The
+    selected value is checked by its rank: fewer than k+1 valid voxels lie
+    below it and more than k lie at or below it.
+    """
+    k = (n_valid - 1) // 2
+    v = cs.select(cube, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        v = cs.select(cube, k)
+    sel_ms = (time.perf_counter() - t0) * 1e3 / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m, nv = cs.median(cube)
+    med_ms = (time.perf_counter() - t0) * 1e3 / reps
+    flat = cube.view(-1)
+    below = int((flat < v).sum())
+    at_or_below = int((flat <= v).sum())
+    n = flat.numel()
+    return {"rank": k, "value": v, "median": m, "n_valid": nv,
+            "select_ms": round(sel_ms, 4), "median_ms": round(med_ms, 4),
+            "select_gbs_3_passes": 3 * 4 * n / (sel_ms * 1e-3) / 1e9,
+            "rank_property_holds": below <= k < at_or_below and nv == n_valid}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,10 +334,15 @@ def main() -> int:
                     help="threads,blocks,hist_copies,unroll override (0 = automatic)")
     ap.add_argument("--only-fused", action="store_true",
                     help="time the fused pass only (for profiler runs)")
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--tune", choices=("table", "run", "off"), default="table",
+                    help="launch shapes: the shipped tuning table (autotune if it is "
+                         "missing), a fresh autotune, or the planner's defaults")
+    ap.add_argument("--tune-save", default="", help="save the tuning table to this path")
+    ap.add_argument("--no-tune", action="store_true", help="same as --tune off")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-item batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-stress", action="store_true", help="skip the 128 GiB stress cube")
+    ap.add_argument("--no-select", action="store_true", help="skip selection and median")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -339,9 +375,19 @@ def main() -> int:
     log(f"stats: n_nan={st0.n_nan} min={lo} max={hi} mean={st0.mean:.6g} std={st0.std:.6g}")
 
     tuned = None
-    if not args.no_tune and not args.launch:
-        tuned = cs.cube_autotune(cube.data_ptr(), dims, cs.CUBE_Q_FUSED, lo, hi, nbins, reps=4)
-        log(f"autotune (fused): {tuned['best']}")
+    mode = "off" if (args.no_tune or args.launch) else args.tune
+    table = os.path.join(ROOT, TUNE_TABLE)
+    if mode == "table" and os.path.exists(table):
+        tuned = {"source": TUNE_TABLE, "entries": cs.cube_tune_load(table)}
+        log(f"tuning table {TUNE_TABLE}: {tuned['entries']} entries")
+    elif mode != "off":
+        tuned = {"source": "autotune"}
+        for kname, kind in (("fused", cs.CUBE_Q_FUSED), ("stats", cs.CUBE_Q_STATS),
+                            ("hist", cs.CUBE_Q_HIST)):
+            tuned[kname] = cs.cube_autotune(cube.data_ptr(), dims, kind, lo, hi, nbins, reps=4)
+            log(f"autotune ({kname}): {tuned[kname]['best']}")
+    if args.tune_save:
+        cs.cube_tune_save(args.tune_save)
 
     stream = torch.cuda.Stream(device=dev)
     out = torch.zeros(64, dtype=torch.uint8, device=dev)
@@ -393,12 +439,17 @@ def main() -> int:
         log(f"{label}: {e:.4f} ms")
 
     if tuned is not None:
-        extra["autotune_fused"] = tuned
+        extra["tuning"] = tuned
     if not args.only_fused and not args.no_batch:
         log("batch64 ...")
         extra["batch64"] = bench_batch64(cs, synth, torch, dev, max(10, args.steps // 2))
         log(f"batch64: graph {extra['batch64']['batched_graph_ms']:.3f} ms vs plain "
             f"{extra['batch64']['plain_ms']:.3f} ms")
+    if not args.only_fused and not args.no_select:
+        sel = bench_select(cs, torch, cube, int(st0.n_valid), 5)
+        extra["select_median"] = sel
+        parity["median_rank_property"] = sel["rank_property_holds"]
+        log(f"select: {sel['select_ms']:.3f} ms, median: {sel['median_ms']:.3f} ms")
     bytes_per_launch = 4 * r.n
     achieved = bytes_per_launch / (ev_ms * 1e-3) / 1e9
     value = r.n / (wall_ms * 1e-3)

@@ -277,6 +277,27 @@ CUBE_API int cube_batch_check(cube_batch_t *b);
  * destroy. */
 CUBE_API int cube_batch_run(const cube_query_t *q, int32_t n);
 
+/*
+ * Out-of-core query over a cube in HOST memory.  The paper's cubes exceed
+ * one device and are processed as sub-cubes while loading overlaps
+ * processing (Sections 2 and 3).  `q->ptr` is host memory (pinned memory
+ * from hipHostMalloc streams at the full link rate; pageable memory is
+ * accepted and staged by the runtime); `q->out` (cube_stats_t) and
+ * `q->counts` (nbins + 3 uint64) are HOST outputs; `q->kind`, `dims`, `lo`,
+ * `hi` and `nbins` mean what they mean for the resident calls.  The box is
+ * cut into chunks of at most `chunk_voxels` voxels (0 = 2^28; allowed
+ * [2^12, 2^31]), runs of whole rows of one plane, each copied by a copy
+ * stream into one of three device buffers while the previous chunk is
+ * processed.  Counts are exact and equal the resident results; statistics
+ * merge the chunks' records in chunk order in FP64 and agree with the
+ * resident results within the moment tolerance.  CUBE_Q_MINMAX reads the
+ * host cube twice.  Synchronous; the library keeps 3 x chunk_voxels x 4
+ * bytes of device memory for later calls (released by cube_shutdown).
+ * Errors: CUBE_EINVAL for a device pointer or the resident calls' argument
+ * errors, CUBE_EDEVICE for a HIP error; calls on one device are serialised.
+ */
+CUBE_API int cube_host_query(const cube_query_t *q, int64_t chunk_voxels);
+
 /* ------------------------------------------------------------------------
  * Query server over cubes resident in GPU memory (the paper's analysis as a
  * service for many users, with batched and real-time requests: Abstract,

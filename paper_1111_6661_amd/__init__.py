@@ -119,6 +119,8 @@ def load() -> C.CDLL:
     lib.cube_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_double)]
     lib.cube_server_latency.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_uint64), i32]
+    lib.cube_host_query.argtypes = [C.POINTER(cube_query_t), i64]
+    lib.cube_host_query.restype = C.c_int
     lib.cube_select.argtypes = [P, I64P, C.c_uint64, C.POINTER(C.c_float)]
     lib.cube_select.restype = C.c_int
     lib.cube_median.argtypes = [P, I64P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
@@ -331,6 +333,48 @@ def make_query(ptr: int, dims, kind: int, nbins: int = 0, lo: float = 0.0, hi: f
     q.kind, q.nbins, q.lo, q.hi = kind, nbins, lo, hi
     q.out, q.counts = out or None, counts or None
     return q
+
+
+def host_box_of(a) -> tuple:
+    """(host address, [nx, ny, nz, sy, sz]) of a float32 numpy array (or CPU
+    tensor) laid out [z, y, x] with unit x-stride."""
+    if not isinstance(a, np.ndarray):
+        a = a.numpy()
+    if a.dtype != np.float32:
+        raise TypeError("cube arrays are float32")
+    if a.ndim == 1:
+        if a.size > 1 and a.strides[0] != 4:
+            raise ValueError("1-D cube arrays must be contiguous")
+        return a.ctypes.data, [a.size, 1, 1, a.size, a.size]
+    if a.ndim != 3:
+        raise ValueError("cube arrays are 1-D or 3-D [z, y, x]")
+    nz, ny, nx = a.shape
+    sz, sy, sx = (s // 4 for s in a.strides)
+    if nx > 1 and sx != 1:
+        raise ValueError("the x axis must have unit stride")
+    return a.ctypes.data, [nx, ny, nz, sy if ny > 1 else nx,
+                           sz if nz > 1 else (sy if ny > 1 else nx) * ny]
+
+
+def cube_host_query(ptr: int, dims, kind: int, nbins: int = 0, lo: float = 0.0,
+                    hi: float = 0.0, chunk_voxels: int = 0):
+    """Out-of-core query over a box in host memory: (Stats or None, counts or
+    None)."""
+    st = cube_stats_t()
+    cnt = np.zeros(max(nbins, 0) + 3, dtype=np.uint64)
+    want_stats = kind != CUBE_Q_HIST
+    want_hist = kind != CUBE_Q_STATS
+    q = make_query(ptr, dims, kind, nbins, lo, hi,
+                   C.addressof(st) if want_stats else 0,
+                   cnt.ctypes.data if want_hist else 0)
+    _check(load().cube_host_query(C.byref(q), chunk_voxels))
+    return (Stats.from_c(st) if want_stats else None), (cnt if want_hist else None)
+
+
+def host_query(a, kind: int, nbins: int = 0, lo: float = 0.0, hi: float = 0.0,
+               chunk_voxels: int = 0):
+    ptr, d = host_box_of(a)
+    return cube_host_query(ptr, d, kind, nbins, lo, hi, chunk_voxels)
 
 
 class Batch:

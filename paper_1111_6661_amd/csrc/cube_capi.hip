@@ -431,6 +431,32 @@ int run_async(Op op, const float *ptr, const int64_t *dims, float lo, float hi, 
     return launch(a, p, stats, s);
 }
 
+int run_pass(const Box &b, bool stats, bool hist, int nbins, const HistRange &range,
+             const HistRange *dev_range, cube_stats_t *dev_out, unsigned long long *dev_counts,
+             bool accumulate, hipStream_t s)
+{
+    if (b.n == 0) return fail(CUBE_EINVAL, "run_pass on an empty box");
+    Workspace *w = nullptr;
+    int rc = get_ws(s, &w);
+    if (rc) return rc;
+    Plan p;
+    if ((rc = make_plan(b, stats, hist ? 1 : 0, nbins, &p))) return rc;
+    PassArgs a = base_args(w, p, nbins);
+    a.range = range;
+    a.dev_range = dev_range;
+    a.out = stats ? dev_out : nullptr;
+    a.counts = hist ? dev_counts : nullptr;
+    a.accumulate = accumulate ? 1 : 0;
+    return launch(a, p, stats, s);
+}
+
+int write_empty(cube_stats_t *dev_out, unsigned long long *dev_counts, int nbins, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_write_empty, dim3(1), dim3(256), 0, s, dev_out, dev_counts, nbins);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CUBE_OK : hip_fail(e, "empty-box launch");
+}
+
 // Argument checks that need no GPU: done before any HIP call.
 int precheck(Op op, const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins)
 {
@@ -581,6 +607,7 @@ int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_
 
 void cube_shutdown(void)
 {
+    host_release();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &kv : g_ws) free_ws(kv.second);
     g_ws.clear();

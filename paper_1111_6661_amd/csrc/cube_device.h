@@ -455,6 +455,30 @@ __device__ __forceinline__ void hist_flush(const unsigned int *lds, int nbins, i
     }
 }
 
+// The [min, max] histogram range with its FP32 scale, formed from the data
+// extrema exactly as the host forms a given range: ok = 1 valid, 0 invalid
+// (infinite extrema, or a width or scale that overflows), 2 no valid voxel.
+__device__ __forceinline__ HistRange range_of_extrema(float fmn, float fmx, unsigned long long nv,
+                                                      int nbins)
+{
+    HistRange r = {qnan(), qnan(), 0.f, 2};
+    if (nv == 0) return r;
+    r.ok = 0;
+    if (isfinite(fmn) && isfinite(fmx)) {
+        const float w = __fsub_rn(fmx, fmn);
+        if (isfinite(w)) {
+            const float sc = w == 0.f ? 0.f : __fdiv_rn((float)nbins, w);
+            if (isfinite(sc)) {
+                r.lo = fmn;
+                r.hi = fmx;
+                r.scale = sc;
+                r.ok = 1;
+            }
+        }
+    }
+    return r;
+}
+
 // The global stage of a stats pass: merge `n_recs` records (all threads of
 // the block call it), then thread 0 writes the result and, when `range_out`
 // is given, the [min, max] histogram range with its FP32 scale.  Returns the
@@ -496,42 +520,29 @@ __device__ void finish_stats(const WaveRec *recs, int n_recs, int accum_mode,
                                                    : (double)sqrtf((float)o.m2 / (float)nv);
     }
     if (range_out) {
-        HistRange r = {qnan(), qnan(), 0.f, 2};
-        if (nv != 0) {
-            r.ok = 0;
-            if (isfinite(fmn) && isfinite(fmx)) {
-                const float w = __fsub_rn(fmx, fmn);
-                if (isfinite(w)) {
-                    const float sc = w == 0.f ? 0.f : __fdiv_rn((float)nbins, w);
-                    if (isfinite(sc)) {
-                        r.lo = fmn;
-                        r.hi = fmx;
-                        r.scale = sc;
-                        r.ok = 1;
-                    }
-                }
-            }
-            if (r.ok == 0) o.flags |= CUBE_HIST_BAD_RANGE;
-        }
+        const HistRange r = range_of_extrema(fmn, fmx, nv, nbins);
+        if (r.ok == 0) o.flags |= CUBE_HIST_BAD_RANGE;
         *range_out = r;
     }
     *out = o;
 }
 
-// Copy the global accumulators to the caller's counts and return them to
-// zero; thread 0 writes below / above / NaN.
+// Copy the global accumulators to the caller's counts (or, with `add`, add
+// them to the counts already there) and return them to zero; thread 0 writes
+// below / above / NaN.
 __device__ __forceinline__ void finish_hist(unsigned long long *acc, unsigned long long *counts,
                                             int nbins, bool on, unsigned long long below,
-                                            unsigned long long above, unsigned long long n_nan)
+                                            unsigned long long above, unsigned long long n_nan,
+                                            bool add = false)
 {
     for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
-        counts[b] = acc[b];
+        counts[b] = (add ? counts[b] : 0ull) + acc[b];
         acc[b] = 0ull;
     }
     if (threadIdx.x == 0) {
-        counts[nbins] = on ? below : 0ull;
-        counts[nbins + 1] = on ? above : 0ull;
-        counts[nbins + 2] = n_nan;
+        counts[nbins] = (add ? counts[nbins] : 0ull) + (on ? below : 0ull);
+        counts[nbins + 1] = (add ? counts[nbins + 1] : 0ull) + (on ? above : 0ull);
+        counts[nbins + 2] = (add ? counts[nbins + 2] : 0ull) + n_nan;
     }
 }
 

@@ -52,6 +52,7 @@ struct PassArgs {
     HistRange *out_range;        // device [min, max] range (two-pass pass 1)
     int32_t accum_mode;          // CUBE_ACCUM_*
     int32_t want_range;          // pass 1 of a two-pass call: write out_range
+    int32_t accumulate;          // add the counts to `counts` instead of writing them
 };
 
 // Kernel launchers (cube_kernels.hip).  `stats`: compute the statistics;
@@ -93,6 +94,20 @@ void collapse(const Box &b, Geom *g);
 int cu_count();
 int accum_mode();
 void get_launch(int *threads, int *blocks, int *copies, int *unroll);
+
+// One pass over a validated device box on stream `s`, with the calling
+// stream's workspace: statistics (to dev_out) and/or a histogram (HIST_NONE
+// or HIST_LDS requested) over `range`, or over `dev_range` when it is not
+// null; with `accumulate` the counts are added to dev_counts.  The box must
+// hold at least one voxel.
+int run_pass(const Box &b, bool stats, bool hist, int nbins, const HistRange &range,
+             const HistRange *dev_range, cube_stats_t *dev_out, unsigned long long *dev_counts,
+             bool accumulate, hipStream_t s);
+// The empty-box results (n_total 0, NaN statistics, zero counts) on `s`.
+int write_empty(cube_stats_t *dev_out, unsigned long long *dev_counts, int nbins, hipStream_t s);
+
+// Release the out-of-core streaming buffers and streams (cube_host.hip).
+void host_release();
 
 // A launch shape chosen by the autotuner (cube_tune.hip).
 struct TunedShape {

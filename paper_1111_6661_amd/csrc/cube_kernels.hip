@@ -67,7 +67,8 @@ __global__ void __launch_bounds__(1024) k_pass(PassArgs a)
         above = S.above;
     }
     if (HIST != HIST_NONE)
-        finish_hist(a.hist_acc, a.counts, a.nbins, hist_on, below, above, g.n_total - nv);
+        finish_hist(a.hist_acc, a.counts, a.nbins, hist_on, below, above, g.n_total - nv,
+                    a.accumulate != 0);
     if (tid == 0) *a.ticket = 0u;
 }
 

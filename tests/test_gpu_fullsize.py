@@ -48,6 +48,9 @@ def test_brick16g_full_cube(cs):
     st_fused_ref = cs.stats(t)
     st, counts = cs.stats_hist(t, st_fused_ref.min, st_fused_ref.max, nb)
     st2, counts2 = cs.stats_hist_minmax(t, nb)
+    k_mid = (int(st_fused_ref.n_valid) - 1) // 2
+    sel = {k: cs.select(t, k) for k in (0, k_mid, int(st_fused_ref.n_valid) - 1)}
+    med, med_nv = cs.median(t)
     t0 = time.perf_counter()
     host = _host_copy(t)
     del t
@@ -61,6 +64,20 @@ def test_brick16g_full_cube(cs):
     assert_counts_match(counts, want, "fused counts")
     assert_counts_match(counts2, want, "two-pass counts")
     assert int(want.sum()) == r.n
+    # Selection at full size, by the rank property that fixes the k-th
+    # smallest: at most k valid voxels lie below it and more than k at or
+    # below it (so it is one of the voxels).  The extremes are the min/max.
+    assert sel[0] == ref.min and sel[int(ref.n_valid) - 1] == ref.max
+    v = sel[k_mid]
+    below = int(np.count_nonzero(host < v))
+    at_or_below = int(np.count_nonzero(host <= v))
+    assert below <= k_mid < at_or_below, (v, below, at_or_below, k_mid)
+    assert med_nv == ref.n_valid
+    if ref.n_valid % 2:
+        assert med == v
+    else:
+        upper = float(np.min(host[host > v])) if at_or_below == k_mid + 1 else v
+        assert med == (float(v) + upper) / 2.0
 
 
 @pytest.mark.timeout(600)
