@@ -9,7 +9,10 @@
 // block of a pass scans that pass's histogram, picks the bin holding the
 // wanted rank, extends the prefix and lowers the rank, on the device, so the
 // host never waits between passes.  After the third pass the prefix is the
-// whole key of the selected voxel.  Counting uses the same lane-interleaved
+// whole key of the selected voxel.  For the median of an even count the
+// upper middle comes from the same passes (the same key again, or the next
+// non-empty key of the last histogram) or, failing both, from one more pass
+// that takes the smallest valid key above the lower middle.  Counting uses the same lane-interleaved
 // LDS sub-histograms as the statistics pass, flushed with one 64-bit atomic
 // per non-empty bin per block.
 #include <string.h>
@@ -26,8 +29,12 @@ struct SelectState {
     unsigned int prefix;         // key bits chosen so far
     unsigned int error;          // 1: rank >= n_valid
     float value;                 // the selected voxel (after the last pass)
-    unsigned int rank_mode;      // 0: `rank` as given; 1: (n_valid - 1) / 2;
-                                 // 2: n_valid / 2 (set once n_valid is known)
+    unsigned int rank_mode;      // 0: `rank` as given; 1: the median, rank
+                                 // (n_valid - 1) / 2 set once n_valid is known
+    unsigned int want_next;      // also find the voxel of the next rank
+    unsigned int need_next;      // ...which the last histogram did not hold
+    unsigned int next_key;       // smallest key above the selected one (min)
+    float value_next;            // the voxel of the next rank
 };
 
 struct SelectArgs {
@@ -85,6 +92,97 @@ __device__ __forceinline__ void select_step(const float (&x)[NV], unsigned long 
     valid += cv;
 }
 
+// Visit every voxel of the box once, in tiles of float4 loads; `step` is
+// called with arrays of 1, 4 or 4 * SEL_U voxels (blank lanes padded with
+// NaN), uniformly across each wavefront.
+template <class Step>
+__device__ __forceinline__ void scan_box(const Geom &g, Step &step)
+{
+    const int tid = threadIdx.x, B = blockDim.x;
+    const unsigned long long G = gridDim.x;
+    const long long u0 = (long long)(((unsigned long long)g.n_units * blockIdx.x) / G);
+    const long long u1 = (long long)(((unsigned long long)g.n_units * (blockIdx.x + 1)) / G);
+    const int lane = tid & 63, wid = tid >> 6;
+    if (u0 >= u1) return;
+    long long row = u0 / g.segs;
+    long long s = u0 - row * g.segs;
+    long long y = row % g.ny;
+    long long z = row / g.ny;
+    for (long long u = u0; u < u1; ++u) {
+        const float *q = g.ptr + y * g.sy + z * g.sz + s * g.seg_len;
+        const long long c0 = s * g.seg_len;
+        const long long len = min(g.seg_len, g.row_len - c0);
+        const long long mis = (long long)((16 - ((uintptr_t)q & 15)) & 15) >> 2;
+        const long long h = min(len, mis);
+        const long long n4 = (len - h) >> 2;
+        const long long t = len - h - 4 * n4;
+        if (wid == 0 && h + t > 0) {
+            long long idx = lane < h ? lane : h + 4 * n4 + (lane - h);
+            const bool have = lane < h + t;
+            idx = have ? idx : 0;
+            const float v = q[idx];
+            float xv[1] = {have ? v : qnan()};
+            step(xv);
+        }
+        const f4 *q4 = (const f4 *)(q + h);
+        const long long T = (long long)B * SEL_U;
+        long long i0 = 0;
+        for (; i0 + T <= n4; i0 += T) {
+            f4 v[SEL_U];
+            load_tile<SEL_U>(v, q4, i0, B, tid);
+            float xv[4 * SEL_U];
+#pragma unroll
+            for (int k = 0; k < SEL_U; ++k) {
+                xv[4 * k + 0] = v[k].x;
+                xv[4 * k + 1] = v[k].y;
+                xv[4 * k + 2] = v[k].z;
+                xv[4 * k + 3] = v[k].w;
+            }
+            step(xv);
+        }
+        for (; i0 < n4; i0 += B) {
+            const long long i = i0 + tid;
+            const bool have = i < n4;
+            const f4 v = __builtin_nontemporal_load(q4 + (have ? i : n4 - 1));
+            float xv[4] = {have ? v.x : qnan(), have ? v.y : qnan(), have ? v.z : qnan(),
+                           have ? v.w : qnan()};
+            step(xv);
+        }
+        if (++s == g.segs) {
+            s = 0;
+            if (++y == g.ny) {
+                y = 0;
+                ++z;
+            }
+        }
+    }
+}
+
+// Counting step of a select pass.
+struct CountStep {
+    SelCtx c;
+    unsigned long long valid;
+    template <int NV>
+    __device__ __forceinline__ void operator()(const float (&x)[NV])
+    {
+        select_step<NV>(x, valid, c);
+    }
+};
+
+// The smallest order key above K among valid voxels (per lane).
+struct NextStep {
+    unsigned int K, m;
+    template <int NV>
+    __device__ __forceinline__ void operator()(const float (&x)[NV])
+    {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const unsigned int k = order_key(x[j]);
+            m = (x[j] == x[j] && k > K && k < m) ? k : m;
+        }
+    }
+};
+
 __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
 {
     extern __shared__ unsigned int lds[];
@@ -94,7 +192,8 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
     const int p = a.pass;
     const int width = sel_width(p);
     const int nbins = 1 << width;
-    SelCtx c;
+    CountStep cs;
+    SelCtx &c = cs.c;
     const int top = sel_shift(p) + width;   // first key bit above this pass's bins
     c.hi_mask = p == 0 ? 0u : (0xffffffffu << top);
     c.prefix_hi = p == 0 ? 0u : (a.st->prefix << top);
@@ -105,67 +204,10 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
     c.base = (C + (tid & 63 & (C - 1))) * 4;
     c.lds = lds;
     lds_zero(lds, nbins, a.copies_log2);
-
-    unsigned long long valid = 0;
-    const Geom &g = a.g;
-    const unsigned long long G = gridDim.x;
-    const long long u0 = (long long)(((unsigned long long)g.n_units * blockIdx.x) / G);
-    const long long u1 = (long long)(((unsigned long long)g.n_units * (blockIdx.x + 1)) / G);
-    const int lane = tid & 63, wid = tid >> 6;
-    if (u0 < u1) {
-        long long row = u0 / g.segs;
-        long long s = u0 - row * g.segs;
-        long long y = row % g.ny;
-        long long z = row / g.ny;
-        for (long long u = u0; u < u1; ++u) {
-            const float *q = g.ptr + y * g.sy + z * g.sz + s * g.seg_len;
-            const long long c0 = s * g.seg_len;
-            const long long len = min(g.seg_len, g.row_len - c0);
-            const long long mis = (long long)((16 - ((uintptr_t)q & 15)) & 15) >> 2;
-            const long long h = min(len, mis);
-            const long long n4 = (len - h) >> 2;
-            const long long t = len - h - 4 * n4;
-            if (wid == 0 && h + t > 0) {
-                long long idx = lane < h ? lane : h + 4 * n4 + (lane - h);
-                const bool have = lane < h + t;
-                idx = have ? idx : 0;
-                const float v = q[idx];
-                float xv[1] = {have ? v : qnan()};
-                select_step<1>(xv, valid, c);
-            }
-            const f4 *q4 = (const f4 *)(q + h);
-            const long long T = (long long)B * SEL_U;
-            long long i0 = 0;
-            for (; i0 + T <= n4; i0 += T) {
-                f4 v[SEL_U];
-                load_tile<SEL_U>(v, q4, i0, B, tid);
-                float xv[4 * SEL_U];
-#pragma unroll
-                for (int k = 0; k < SEL_U; ++k) {
-                    xv[4 * k + 0] = v[k].x;
-                    xv[4 * k + 1] = v[k].y;
-                    xv[4 * k + 2] = v[k].z;
-                    xv[4 * k + 3] = v[k].w;
-                }
-                select_step<4 * SEL_U>(xv, valid, c);
-            }
-            for (; i0 < n4; i0 += B) {
-                const long long i = i0 + tid;
-                const bool have = i < n4;
-                const f4 v = __builtin_nontemporal_load(q4 + (have ? i : n4 - 1));
-                float xv[4] = {have ? v.x : qnan(), have ? v.y : qnan(), have ? v.z : qnan(),
-                               have ? v.w : qnan()};
-                select_step<4>(xv, valid, c);
-            }
-            if (++s == g.segs) {
-                s = 0;
-                if (++y == g.ny) {
-                    y = 0;
-                    ++z;
-                }
-            }
-        }
-    }
+    cs.valid = 0;
+    scan_box(a.g, cs);
+    const unsigned long long valid = cs.valid;
+    const int lane = tid & 63;
     // Flush bins (slot b + 1 holds bin b); the valid count goes with the
     // first pass.
     __syncthreads();
@@ -196,20 +238,39 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
     __syncthreads();
     if (tid == 0) {
         SelectState st = *a.st;
-        if (p == 0 && st.rank_mode == 1 && st.n_valid) st.rank = (st.n_valid - 1) / 2;
-        if (p == 0 && st.rank_mode == 2) st.rank = st.n_valid / 2;
+        if (p == 0 && st.rank_mode == 1 && st.n_valid) {
+            st.rank = (st.n_valid - 1) / 2;
+            st.want_next = (st.n_valid % 2 == 0) ? 1u : 0u;
+        }
         if (p == 0 && st.rank >= st.n_valid) st.error = 1u;
+        if (p == 0 && st.want_next && st.rank + 1 >= st.n_valid) st.want_next = 0u;
         if (!st.error) {
             unsigned long long before = 0;
             int t = 0;
             while (t < B - 1 && before + s_part[t] <= st.rank) before += s_part[t++];
             int b = t * per;
             while (b < nbins - 1 && before + a.acc[b] <= st.rank) before += a.acc[b++];
-            st.prefix = (st.prefix << width) | (unsigned int)b;
+            const unsigned int up = st.prefix << width;
+            st.prefix = up | (unsigned int)b;
             st.rank -= before;
             if (p == 2) {
                 st.value = key_value(st.prefix);
                 if (a.out) *a.out = st.value;
+                if (st.want_next) {
+                    // The next rank is this key again, the next non-empty
+                    // key of this histogram, or (neither) the smallest key
+                    // above this one anywhere: one more pass.
+                    if (st.rank + 1 < a.acc[b]) {
+                        st.value_next = st.value;
+                    } else {
+                        int nb = b + 1;
+                        while (nb < nbins && a.acc[nb] == 0ull) ++nb;
+                        if (nb < nbins)
+                            st.value_next = key_value(up | (unsigned int)nb);
+                        else
+                            st.need_next = 1u;
+                    }
+                }
             }
         }
         *a.st = st;
@@ -217,6 +278,37 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
     __syncthreads();
     for (int b = tid; b < nbins; b += B) a.acc[b] = 0ull;
     if (tid == 0) *a.ticket = 0u;
+}
+
+// The voxel of the next rank when the last histogram did not hold it: the
+// smallest valid key above the selected one.  Every block exits at once
+// unless it is needed.
+__global__ void __launch_bounds__(1024) k_select_next(SelectArgs a)
+{
+    __shared__ unsigned int s_last;
+    const int tid = threadIdx.x;
+    if (!a.st->need_next || a.st->error) return;
+    NextStep ns;
+    ns.K = a.st->prefix;
+    ns.m = 0xffffffffu;
+    scan_box(a.g, ns);
+    unsigned int m = ns.m;
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned int o = __shfl_xor(m, off);
+        m = o < m ? o : m;
+    }
+    if ((tid & 63) == 0 && m != 0xffffffffu) atomicMin(&a.st->next_key, m);
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        s_last = (atomicAdd(a.ticket, 1u) == (unsigned int)(gridDim.x - 1));
+    }
+    __syncthreads();
+    if (!s_last || tid != 0) return;
+    __threadfence();
+    a.st->value_next = key_value(__hip_atomic_load(&a.st->next_key, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT));
+    *a.ticket = 0u;
 }
 
 }  // namespace cube
@@ -258,9 +350,12 @@ int select_ws(SelectWorkspace **out)
     return CUBE_OK;
 }
 
-// Three passes on the default stream; the result is read back.  With
-// rank_mode 1 or 2 the rank is the lower / upper middle of the valid voxels.
-int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64_t *n_valid)
+// Three passes on the default stream (and, for the median of an even count,
+// at most one more); the result is read back.  With rank_mode 1 the rank is
+// the lower middle of the valid voxels and, for an even count, *next is the
+// upper middle.
+int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64_t *n_valid,
+                float *next = nullptr)
 {
     SelectWorkspace *w = nullptr;
     int rc = select_ws(&w);
@@ -269,6 +364,7 @@ int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64
     memset(&init, 0, sizeof init);
     init.rank = rank;
     init.rank_mode = (unsigned int)rank_mode;
+    init.next_key = 0xffffffffu;
     hipError_t e;
     // Synchronous copy: the workspace is reused by the next call.
     if ((e = hipMemcpy(w->st, &init, sizeof init, hipMemcpyHostToDevice)) != hipSuccess)
@@ -304,6 +400,14 @@ int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64
             hipSuccess)
             return hip_fail(e, "select launch");
     }
+    if (rank_mode == 1) {
+        SelectArgs ac = a;
+        void *args[] = {&ac};
+        if ((e = hipLaunchKernel(reinterpret_cast<const void *>(&k_select_next),
+                                 dim3((unsigned)blocks), dim3(threads), args, 0, nullptr)) !=
+            hipSuccess)
+            return hip_fail(e, "select launch");
+    }
     if ((e = hipMemcpy(w->h_st, w->st, sizeof(SelectState), hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(e, "select result");
     if (n_valid) *n_valid = w->h_st->n_valid;
@@ -311,6 +415,7 @@ int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64
         return fail(CUBE_EINVAL, "rank %llu >= %llu valid voxels", (unsigned long long)rank,
                     (unsigned long long)w->h_st->n_valid);
     *value = w->h_st->value;
+    if (next) *next = w->h_st->want_next ? w->h_st->value_next : w->h_st->value;
     return CUBE_OK;
 }
 
@@ -343,16 +448,11 @@ int cube_median(const float *ptr, const int64_t *dims, double *median, uint64_t 
     // n_valid the upper middle too.
     float a = 0.f, c = 0.f;
     uint64_t n = 0;
-    rc = select_rank(b, 0, 1, &a, &n);
+    rc = select_rank(b, 0, 1, &a, &n, &c);
     if (n_valid) *n_valid = n;
     if (n == 0) return fail(CUBE_EINVAL, "no valid voxel");
     if (rc) return rc;
-    if (n % 2 == 1) {
-        *median = (double)a;
-    } else {
-        if ((rc = select_rank(b, 0, 2, &c, nullptr))) return rc;
-        *median = ((double)a + (double)c) / 2.0;
-    }
+    *median = n % 2 == 1 ? (double)a : ((double)a + (double)c) / 2.0;
     return CUBE_OK;
 }
 

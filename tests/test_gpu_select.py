@@ -70,3 +70,22 @@ def test_median_strided_and_ties(cs):
     t = torch.from_numpy(a).cuda()
     assert cs.median(t)[0] == 2.0
     assert cs.select(t, 0) == 1.0 and cs.select(t, a.size - 1) == 3.0
+
+
+def test_median_even_count_upper_middle(cs):
+    """The upper middle of an even count found three ways: the same key
+    again, the next key of the last histogram, and the extra pass for the
+    smallest key above the lower middle."""
+    one_up = np.nextafter(np.float32(1.0), np.float32(2.0))
+    cases = [
+        np.repeat(np.array([1.0, 1.0, 1.0, 3.0], np.float32), 1000),     # same key
+        np.repeat(np.array([1.0, one_up], np.float32), 3000),             # same histogram
+        np.repeat(np.array([1.0, 2.0], np.float32), 5000),                # extra pass
+        np.array([-0.0, 0.0], np.float32),                                # -0 then +0
+        np.array([np.nan, 5.0, np.nan, -7.5, 1e30, -1e-40], np.float32),  # blanks, subnormal
+    ]
+    for a in cases:
+        t = torch.from_numpy(a).cuda()
+        m, nv = cs.median(t)
+        assert nv == int((~np.isnan(a)).sum())
+        assert m == oracle.median(a), (a[:8], m, oracle.median(a))
