@@ -62,6 +62,8 @@ KERNEL_SOURCES = ("paper_1111_6661_amd/csrc/cube_device.h",
 PROFILE_SUMMARY = "profiles/fused_brick16g_trace_and_bytes.md"
 # Launch shapes the autotuner chose on an MI355X for the brick's pass kinds.
 TUNE_TABLE = "paper_1111_6661_amd/tuning/gfx950.json"
+# PCIe 5.0 x16, one direction: 32 GT/s x 16 lanes, 128b/130b coding.
+PCIE_PEAK_GBS = 32e9 * 16 / 8 * 128 / 130 / 1e9
 
 
 def kernel_source_hash() -> str:
@@ -323,6 +325,45 @@ def bench_select(cs, torch, cube, n_valid: int, reps: int):
             "rank_property_holds": below <= k < at_or_below and nv == n_valid}
 
 
+def bench_host(cs, torch, cube, lo: float, hi: float, nbins: int, planes: int, reps: int):
+    """Out-of-core fused queries over a copy of the brick's first planes in
+    host memory: pinned (hipHostMalloc through torch) and pageable (numpy).
+    The link ceiling is a plain 1 GiB pinned host-to-device copy."""
+    import numpy as np
+    sub = cube[:planes]
+    n = sub.numel()
+    pinned = torch.empty(tuple(sub.shape), dtype=torch.float32, pin_memory=True)
+    pinned.copy_(sub)
+    dst = torch.empty(1 << 28, dtype=torch.float32, device=cube.device)
+    src = pinned.view(-1)[:1 << 28]
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 4 * (1 << 28) / (time.perf_counter() - t0) / 1e9
+    del dst
+    st_d, cnt_d = cs.stats_hist(sub, lo, hi, nbins)
+    res = {"planes": planes, "voxels": n, "bytes": 4 * n, "link_copy_gbs": copy_gbs,
+           "link_peak_gbs": PCIE_PEAK_GBS}
+    for label, arr in (("pinned", pinned), ("pageable", None)):
+        if arr is None:
+            arr = pinned.numpy().copy()
+        cs.host_query(arr, cs.CUBE_Q_FUSED, nbins, lo, hi)   # warm-up
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st, cnt = cs.host_query(arr, cs.CUBE_Q_FUSED, nbins, lo, hi)
+        dt = (time.perf_counter() - t0) / reps
+        res[label] = {"s_per_query": dt, "gbs": 4 * n / dt / 1e9,
+                      "frac_of_copy": 4 * n / dt / 1e9 / copy_gbs,
+                      "counts_equal_resident": bool(np.array_equal(cnt, cnt_d)),
+                      "extrema_equal_resident": st.min == st_d.min and st.max == st_d.max,
+                      "std_rel_diff_vs_resident": abs(st.std - st_d.std) / st_d.std}
+        del arr
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,6 +384,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-stress", action="store_true", help="skip the 128 GiB stress cube")
     ap.add_argument("--no-select", action="store_true", help="skip selection and median")
+    ap.add_argument("--no-host", action="store_true", help="skip the out-of-core host queries")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -450,6 +492,13 @@ def main() -> int:
         extra["select_median"] = sel
         parity["median_rank_property"] = sel["rank_property_holds"]
         log(f"select: {sel['select_ms']:.3f} ms, median: {sel['median_ms']:.3f} ms")
+    if not args.only_fused and not args.no_host:
+        hq = bench_host(cs, torch, cube, lo, hi, nbins, 256, 3)
+        extra["host_out_of_core"] = hq
+        parity["host_counts_equal_resident"] = (hq["pinned"]["counts_equal_resident"] and
+                                                hq["pageable"]["counts_equal_resident"])
+        log(f"host streaming: pinned {hq['pinned']['gbs']:.1f} GB/s, pageable "
+            f"{hq['pageable']['gbs']:.1f} GB/s, plain copy {hq['link_copy_gbs']:.1f} GB/s")
     bytes_per_launch = 4 * r.n
     achieved = bytes_per_launch / (ev_ms * 1e-3) / 1e9
     value = r.n / (wall_ms * 1e-3)

@@ -105,6 +105,8 @@ class Oracle:
         lib.oracle_median.argtypes = [P, i64, i64, i64, i64, i64, C.POINTER(f64),
                                       C.POINTER(C.c_uint64)]
         lib.oracle_median.restype = C.c_int
+        lib.oracle_project.argtypes = [P, i64, i64, i64, i64, i64, P, P, P]
+        lib.oracle_project.restype = C.c_int
         self.lib = lib
         self.path = path
 
@@ -151,6 +153,18 @@ class Oracle:
         if self.lib.oracle_median(*box_of(a), C.byref(m), C.byref(n)) != 0:
             raise ValueError("no valid voxel or invalid box")
         return m.value
+
+    def project(self, a: np.ndarray):
+        """(mip float32 [ny, nx], mom0 float64 [ny, nx], nvalid uint32 [ny, nx])
+        of a [z, y, x] array: projections along the channel axis z."""
+        ptr, nx, ny, nz, sy, sz = box_of(a)
+        mip = np.empty((ny, nx), np.float32)
+        mom0 = np.empty((ny, nx), np.float64)
+        nv = np.empty((ny, nx), np.uint32)
+        if self.lib.oracle_project(ptr, nx, ny, nz, sy, sz, mip.ctypes.data, mom0.ctypes.data,
+                                   nv.ctypes.data) != 0:
+            raise ValueError("invalid box")
+        return mip, mom0, nv
 
     def hist_scale(self, lo: float, hi: float, nbins: int) -> float:
         """The FP32 scale nbins / (hi - lo); ValueError on an invalid range."""
@@ -221,6 +235,10 @@ def select(a, k):
 
 def median(a):
     return default().median(a)
+
+
+def project(a):
+    return default().project(a)
 
 
 def box_of(a: np.ndarray):

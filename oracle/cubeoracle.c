@@ -28,6 +28,12 @@
  *                  n_valid, the FP64 mean of select(n/2-1) and select(n/2)
  *                  for even n_valid (the median task of Section 3).
  *
+ *   projections along the channel axis, per spatial pixel (x, y) over the
+ *   channels z of the box (the maps shown beside a rendered cube):
+ *      mip(x, y)    : the maximum valid voxel (-0 < +0), NaN when none
+ *      mom0(x, y)   : the sum of the valid voxels (FP64), NaN when none
+ *      nvalid(x, y) : the number of valid voxels
+ *
  *   histogram over a closed range [lo, hi] with nbins bins, decided in FP32:
  *      blank            -> the NaN counter
  *      x < lo           -> the "below" counter
@@ -332,5 +338,34 @@ int oracle_median(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t sy
         if (oracle_select(p, nx, ny, nz, sy, sz, st.n_valid / 2, &b)) return -1;
         *median = ((double)a + (double)b) / 2.0;
     }
+    return 0;
+}
+
+/*
+ * Projections along the channel axis (see the header): dense nx*ny maps,
+ * pixel (x, y) at index x + nx*y; any output may be NULL.  Returns 0, or -1
+ * for an invalid box.
+ */
+int oracle_project(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t sy,
+                   int64_t sz, float *mip, double *mom0, uint32_t *nvalid)
+{
+    if (!dims_ok(nx, ny, nz, sy, sz)) return -1;
+    for (int64_t y = 0; y < ny; ++y)
+        for (int64_t x = 0; x < nx; ++x) {
+            float mx = NAN;
+            double s = 0.0, c = 0.0;
+            uint32_t n = 0;
+            for (int64_t z = 0; z < nz; ++z) {
+                float f = p[x + sy * y + sz * z];
+                if (f != f) continue;
+                if (n == 0 || before(mx, f)) mx = f;
+                neumaier_add(&s, &c, (double)f);
+                ++n;
+            }
+            const int64_t i = x + nx * y;
+            if (mip) mip[i] = mx;
+            if (mom0) mom0[i] = n ? s + c : NAN;
+            if (nvalid) nvalid[i] = n;
+        }
     return 0;
 }

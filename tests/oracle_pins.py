@@ -24,6 +24,8 @@ import os
 import statistics
 from fractions import Fraction
 
+import warnings
+
 import numpy as np
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -356,7 +358,52 @@ def pin_select(o):
         raise AssertionError("accepted an out-of-range rank")
 
 
+def pin_project(o):
+    """Projections along z against numpy reductions over axis 0, exact sums
+    (math.fsum) and the -0 < +0 order, plus consistency with the global
+    statistics."""
+    import math
+    rng = np.random.default_rng(21)
+    a = (rng.standard_normal((13, 7, 11)) * 3).astype(np.float32)
+    a[rng.random(a.shape) < 0.2] = np.nan
+    a[:, 2, 3] = np.nan                       # an all-blank pixel
+    mip, mom0, nv = o.project(a)
+    assert mip.shape == (7, 11) and mom0.shape == (7, 11) and nv.shape == (7, 11)
+    want_nv = np.count_nonzero(~np.isnan(a), axis=0)
+    assert np.array_equal(nv, want_nv)
+    with np.errstate(invalid="ignore"), warnings.catch_warnings():
+        warnings.simplefilter("ignore", RuntimeWarning)
+        want_mip = np.nanmax(a, axis=0)
+    assert np.array_equal(np.isnan(mip), want_nv == 0)
+    assert np.array_equal(mip[want_nv > 0], want_mip[want_nv > 0])
+    for y in range(7):
+        for x in range(11):
+            col = a[:, y, x]
+            col = col[~np.isnan(col)]
+            if col.size == 0:
+                assert math.isnan(mom0[y, x])
+            else:
+                assert mom0[y, x] == math.fsum(col.astype(np.float64)), (y, x)
+    st = o.stats(a)
+    assert int(nv.sum()) == st.n_valid
+    assert np.nanmax(mip) == st.max
+    assert abs(np.nansum(mom0) - st.mean * st.n_valid) <= 1e-12 * st.mean_abs * st.n_valid
+    # the channel axis is z: a cube constant along y and x but not along z
+    r = np.broadcast_to(np.arange(5, dtype=np.float32)[:, None, None], (5, 3, 4)).copy()
+    mip, mom0, nv = o.project(r)
+    assert (mip == 4.0).all() and (mom0 == 10.0).all() and (nv == 5).all()
+    # signed zeros: +0 is the larger; a lone -0 stays -0
+    z = np.array([[[-0.0, 0.0, -0.0]], [[0.0, -0.0, -0.0]]], dtype=np.float32)
+    mip, _, _ = o.project(z)
+    assert [signbit(v) for v in mip[0]] == [False, False, True]
+    # a strided view equals its contiguous copy
+    big = (rng.standard_normal((9, 12, 15))).astype(np.float32)
+    view = big[1:8, 2:11, 3:14]
+    for u, v in zip(o.project(view), o.project(np.ascontiguousarray(view))):
+        assert np.array_equal(u, v, equal_nan=True)
+
+
 ALL_PINS = [pin_textbook, pin_exact_rational, pin_closed_forms, pin_merge,
             pin_extrema_nan, pin_strided, pin_hist_ramp, pin_hist_unit_scale,
             pin_hist_edges, pin_hist_subnormal, pin_hist_rounding_model, pin_hist_numpy,
-            pin_hist_invariants, pin_hist_validation, pin_select]
+            pin_hist_invariants, pin_hist_validation, pin_select, pin_project]

@@ -45,6 +45,14 @@ MUTANTS = {
     "select_includes_nan": ("if (f == f) v[n++] = f;", "v[n++] = f;"),
     "select_reversed": ("if (before(x, y)) return -1;", "if (before(x, y)) return 1;"),
     "median_upper_only": ("*median = ((double)a + (double)b) / 2.0;", "*median = (double)b;"),
+    "project_wrong_axis": ("float f = p[x + sy * y + sz * z];\n                if (f != f) continue;",
+                           "float f = p[x + sy * z + sz * y];\n                if (f != f) continue;"),
+    "project_min_not_max": ("if (n == 0 || before(mx, f)) mx = f;",
+                            "if (n == 0 || before(f, mx)) mx = f;"),
+    "project_empty_is_zero": ("if (mom0) mom0[i] = n ? s + c : NAN;",
+                              "if (mom0) mom0[i] = s + c;"),
+    "project_counts_blank": ("if (f != f) continue;\n                if (n == 0",
+                             "if (f != f) { ++n; continue; }\n                if (n == 0"),
 }
 
 
