@@ -194,6 +194,27 @@ CUBE_API int cube_median(const float *ptr, const int64_t *dims, double *median,
                          uint64_t *n_valid);
 
 /*
+ * Projections along the channel axis z: the maps a viewer of spectral cubes
+ * shows beside the rendered volume (Section 2).  For every spatial pixel
+ * (x, y) of the box, over its nz channels:
+ *   mip[x + nx*y]     float    the maximum valid voxel (-0 < +0); NaN if none
+ *   mom0[x + nx*y]    double   the sum of the valid voxels over the extended
+ *                              reals (+Inf and -Inf together give NaN); NaN
+ *                              if none.  Times the channel width it is the
+ *                              moment-0 map.
+ *   nvalid[x + nx*y]  uint32   the number of valid channels
+ * The outputs are dense DEVICE arrays of nx*ny elements; any may be NULL but
+ * not all three.  Stream-ordered on `stream` (NULL = the default stream).
+ * Sums are FP64 in channel order within each of at most 64 channel slices,
+ * the slices merged in order; results depend only on the shape.  nz == 0
+ * gives NaN / NaN / 0 maps.  Errors: CUBE_EINVAL for the box errors of the
+ * other calls, outputs that are not device memory of the needed size or are
+ * misaligned (mom0 8-byte), or nz >= 2^32; CUBE_EDEVICE for a HIP error.
+ */
+CUBE_API int cube_project(const float *ptr, const int64_t *dims, float *mip, double *mom0,
+                          uint32_t *nvalid, void *stream);
+
+/*
  * Autotuner.  Times candidate launch shapes (threads, float4 loads per tile,
  * LDS histogram copies, blocks per CU) of one pass kind -- CUBE_Q_STATS,
  * CUBE_Q_HIST or CUBE_Q_FUSED over [lo, hi] -- on the given DEVICE box

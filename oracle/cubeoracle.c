@@ -31,7 +31,8 @@
  *   projections along the channel axis, per spatial pixel (x, y) over the
  *   channels z of the box (the maps shown beside a rendered cube):
  *      mip(x, y)    : the maximum valid voxel (-0 < +0), NaN when none
- *      mom0(x, y)   : the sum of the valid voxels (FP64), NaN when none
+ *      mom0(x, y)   : the sum of the valid voxels (FP64, over the extended
+ *                     reals: +Inf and -Inf together give NaN), NaN when none
  *      nvalid(x, y) : the number of valid voxels
  *
  *   histogram over a closed range [lo, hi] with nbins bins, decided in FP32:
@@ -355,16 +356,23 @@ int oracle_project(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t s
             float mx = NAN;
             double s = 0.0, c = 0.0;
             uint32_t n = 0;
+            int pinf = 0, ninf = 0;
             for (int64_t z = 0; z < nz; ++z) {
                 float f = p[x + sy * y + sz * z];
                 if (f != f) continue;
                 if (n == 0 || before(mx, f)) mx = f;
-                neumaier_add(&s, &c, (double)f);
+                /* the sum over the extended reals: infinities apart */
+                if (isinf(f))
+                    *(f > 0 ? &pinf : &ninf) = 1;
+                else
+                    neumaier_add(&s, &c, (double)f);
                 ++n;
             }
+            double sum = s + c;
+            if (pinf || ninf) sum = (pinf && ninf) ? NAN : (pinf ? INFINITY : -INFINITY);
             const int64_t i = x + nx * y;
             if (mip) mip[i] = mx;
-            if (mom0) mom0[i] = n ? s + c : NAN;
+            if (mom0) mom0[i] = n ? sum : NAN;
             if (nvalid) nvalid[i] = n;
         }
     return 0;

@@ -119,6 +119,8 @@ def load() -> C.CDLL:
     lib.cube_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_double)]
     lib.cube_server_latency.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_uint64), i32]
+    lib.cube_project.argtypes = [P, I64P, P, P, P, P]
+    lib.cube_project.restype = C.c_int
     lib.cube_host_query.argtypes = [C.POINTER(cube_query_t), i64]
     lib.cube_host_query.restype = C.c_int
     lib.cube_select.argtypes = [P, I64P, C.c_uint64, C.POINTER(C.c_float)]
@@ -333,6 +335,29 @@ def make_query(ptr: int, dims, kind: int, nbins: int = 0, lo: float = 0.0, hi: f
     q.kind, q.nbins, q.lo, q.hi = kind, nbins, lo, hi
     q.out, q.counts = out or None, counts or None
     return q
+
+
+def cube_project(ptr: int, dims, mip: int = 0, mom0: int = 0, nvalid: int = 0,
+                 stream: int = 0) -> None:
+    """Projections along z into device maps (addresses; 0 = not wanted)."""
+    _check(load().cube_project(C.c_void_p(ptr), _dims(dims), C.c_void_p(mip or None),
+                               C.c_void_p(mom0 or None), C.c_void_p(nvalid or None),
+                               C.c_void_p(stream or None)))
+
+
+def project(t):
+    """(mip float32 [ny, nx], mom0 float64 [ny, nx], nvalid int32-viewed uint32
+    [ny, nx]) device tensors of a [z, y, x] CUDA tensor, on the current
+    stream."""
+    import torch
+    ptr, d = box_of(t)
+    nx, ny = d[0], d[1]
+    mip = torch.empty((ny, nx), dtype=torch.float32, device=t.device)
+    mom0 = torch.empty((ny, nx), dtype=torch.float64, device=t.device)
+    nv = torch.empty((ny, nx), dtype=torch.int32, device=t.device)
+    cube_project(ptr, d, mip.data_ptr(), mom0.data_ptr(), nv.data_ptr(),
+                 torch.cuda.current_stream(t.device).cuda_stream)
+    return mip, mom0, nv
 
 
 def host_box_of(a) -> tuple:

@@ -108,6 +108,8 @@ int write_empty(cube_stats_t *dev_out, unsigned long long *dev_counts, int nbins
 
 // Release the out-of-core streaming buffers and streams (cube_host.hip).
 void host_release();
+// Release the projection slice partials (cube_project.hip).
+void project_release();
 
 // A launch shape chosen by the autotuner (cube_tune.hip).
 struct TunedShape {

@@ -396,6 +396,13 @@ def pin_project(o):
     z = np.array([[[-0.0, 0.0, -0.0]], [[0.0, -0.0, -0.0]]], dtype=np.float32)
     mip, _, _ = o.project(z)
     assert [signbit(v) for v in mip[0]] == [False, False, True]
+    # infinities: the sum over the extended reals
+    w = np.array([[[1.0, np.inf, -np.inf, np.inf]], [[2.0, 5.0, 3.0, -np.inf]],
+                  [[np.nan, 1.0, -1.0, 7.0]]], dtype=np.float32)
+    mip, mom0, nv = o.project(w)
+    assert mom0[0, 0] == 3.0 and mom0[0, 1] == np.inf and mom0[0, 2] == -np.inf
+    assert math.isnan(mom0[0, 3]) and mip[0, 3] == np.inf and mip[0, 2] == 3.0
+    assert list(nv[0]) == [2, 3, 3, 3]
     # a strided view equals its contiguous copy
     big = (rng.standard_normal((9, 12, 15))).astype(np.float32)
     view = big[1:8, 2:11, 3:14]

@@ -49,8 +49,10 @@ MUTANTS = {
                            "float f = p[x + sy * z + sz * y];\n                if (f != f) continue;"),
     "project_min_not_max": ("if (n == 0 || before(mx, f)) mx = f;",
                             "if (n == 0 || before(f, mx)) mx = f;"),
-    "project_empty_is_zero": ("if (mom0) mom0[i] = n ? s + c : NAN;",
-                              "if (mom0) mom0[i] = s + c;"),
+    "project_empty_is_zero": ("if (mom0) mom0[i] = n ? sum : NAN;",
+                              "if (mom0) mom0[i] = sum;"),
+    "project_inf_cancel": ("sum = (pinf && ninf) ? NAN : (pinf ? INFINITY : -INFINITY);",
+                           "sum = pinf ? INFINITY : -INFINITY;"),
     "project_counts_blank": ("if (f != f) continue;\n                if (n == 0",
                              "if (f != f) { ++n; continue; }\n                if (n == 0"),
 }
