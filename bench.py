@@ -325,6 +325,27 @@ def bench_select(cs, torch, cube, n_valid: int, reps: int):
             "rank_property_holds": below <= k < at_or_below and nv == n_valid}
 
 
+def bench_project(cs, torch, cube, stream, steps: int):
+    """Channel-axis projections of the brick: maximum, FP64 sum and valid
+    count per pixel in one read (4 B per voxel in, 16 B per pixel out)."""
+    nz, ny, nx = cube.shape
+    ptr, d = cs.box_of(cube)
+    mip = torch.empty((ny, nx), dtype=torch.float32, device=cube.device)
+    mom0 = torch.empty((ny, nx), dtype=torch.float64, device=cube.device)
+    nv = torch.empty((ny, nx), dtype=torch.int32, device=cube.device)
+    sp = stream.cuda_stream
+
+    def run():
+        cs.cube_project(ptr, d, mip.data_ptr(), mom0.data_ptr(), nv.data_ptr(), sp)
+
+    _, ev = time_launches(run, stream, steps, 2)
+    torch.cuda.synchronize()
+    nbytes = 4 * cube.numel() + 16 * nx * ny
+    gbs = nbytes / (ev * 1e-3) / 1e9
+    return {"ms": round(ev, 4), "gbs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+            "bytes_per_call": nbytes, "valid_total": int(nv.to(torch.int64).sum())}
+
+
 def bench_host(cs, torch, cube, lo: float, hi: float, nbins: int, planes: int, reps: int):
     """Out-of-core fused queries over a copy of the brick's first planes in
     host memory: pinned (hipHostMalloc through torch) and pageable (numpy).
@@ -492,6 +513,11 @@ def main() -> int:
         extra["select_median"] = sel
         parity["median_rank_property"] = sel["rank_property_holds"]
         log(f"select: {sel['select_ms']:.3f} ms, median: {sel['median_ms']:.3f} ms")
+    if not args.only_fused:
+        pj = bench_project(cs, torch, cube, stream, n_short)
+        extra["project"] = pj
+        parity["project_valid_total_equals_stats"] = pj.pop("valid_total") == st0.n_valid
+        log(f"project: {pj['ms']:.3f} ms ({100 * pj['frac_hbm_peak']:.1f} % of HBM peak)")
     if not args.only_fused and not args.no_host:
         hq = bench_host(cs, torch, cube, lo, hi, nbins, 256, 3)
         extra["host_out_of_core"] = hq

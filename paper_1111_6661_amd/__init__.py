@@ -374,6 +374,8 @@ def host_box_of(a) -> tuple:
     if a.ndim != 3:
         raise ValueError("cube arrays are 1-D or 3-D [z, y, x]")
     nz, ny, nx = a.shape
+    if a.size == 0:
+        return a.ctypes.data, [nx, ny, nz, 0, 0]
     sz, sy, sx = (s // 4 for s in a.strides)
     if nx > 1 and sx != 1:
         raise ValueError("the x axis must have unit stride")
