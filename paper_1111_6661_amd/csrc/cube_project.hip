@@ -6,9 +6,12 @@
 // moment-0 map up to the channel width) and the number of valid channels.
 // One streaming read of the cube makes all three.
 //
-// Each lane owns V adjacent pixels of one row (V = 4 when rows, planes and the
-// base are 16-byte aligned, else 1) and walks the channels; per channel a
-// wavefront reads 64 * 4 * V contiguous bytes, four channels in flight.  The
+// When the rows are contiguous and 16-byte aligned, lanes own quads of pixels
+// numbered over the whole image, Q quads per lane 1 KB apart, so that per
+// channel a wavefront reads Q KB of contiguous memory (k_project_quads).
+// Otherwise each lane owns V adjacent pixels of one row (V = 4 when rows,
+// planes and the base are 16-byte aligned, else 1), four channels in flight
+// (k_project).  Each lane walks the channels of its pixels.  The
 // sums are taken in FP64: on CDNA4 an FP64 add issues at the rate of an FP32
 // add, so this costs no more than compensated FP32 and is exact to about
 // n * 2^-53.  When the image has too few pixels to fill the device the
@@ -31,6 +34,7 @@ struct ProjArgs {
     const float *ptr;
     int64_t nx, ny, nz, sy, sz;
     int64_t units;           // lanes' work items: pixels (V = 1) or quads (V = 4)
+    int64_t u0;              // k_project: first unit; k_project_quads: units it covers
     int64_t zps;             // channels per slice
     int32_t slices;
     float *mip;              // outputs, dense nx * ny (any may be null)
@@ -47,7 +51,7 @@ constexpr int PROJ_ZU = 4;
 template <int V>
 __global__ void __launch_bounds__(PROJ_THREADS) k_project(ProjArgs a)
 {
-    const int64_t u = (int64_t)blockIdx.x * PROJ_THREADS + threadIdx.x;
+    const int64_t u = a.u0 + (int64_t)blockIdx.x * PROJ_THREADS + threadIdx.x;
     if (u >= a.units) return;
     const int64_t row_units = a.nx / V;
     const int64_t y = u / row_units;
@@ -114,6 +118,69 @@ __global__ void __launch_bounds__(PROJ_THREADS) k_project(ProjArgs a)
             a.p_max[o + k] = m[k];
             a.p_sum[o + k] = s[k];
             a.p_cnt[o + k] = n[k];
+        }
+    }
+}
+
+// The fast path for images whose rows are contiguous and 16-byte aligned:
+// pixel quads are numbered over the whole image, and wavefront w owns quads
+// [64 Q w, 64 Q (w + 1)), lane l the quads 64 k + l.  Per channel a wavefront
+// then reads Q runs of 1 KB that together cover 1 KB * Q of contiguous
+// memory, which keeps HBM pages open far better than 1 KB per wavefront.
+template <int Q>
+__global__ void __launch_bounds__(PROJ_THREADS) k_project_quads(ProjArgs a)
+{
+    // Launched for whole wavefronts only; the remaining quads go to k_project.
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * PROJ_THREADS + threadIdx.x) >> 6;
+    const int64_t qb = wave * 64 * Q;
+    if (qb + 64 * Q > a.u0) return;
+    const int64_t z0 = (int64_t)blockIdx.y * a.zps;
+    const int64_t z1 = min(a.nz, z0 + a.zps);
+    const int64_t sz4 = a.sz >> 2;
+    const f4 *q = (const f4 *)a.ptr + qb + lane + z0 * sz4;
+    float m[Q][4];
+    double s[Q][4];
+    uint32_t n[Q][4];
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            m[k][j] = -INFINITY;
+            s[k][j] = 0.0;
+            n[k][j] = 0u;
+        }
+    for (int64_t z = z0; z < z1; ++z) {
+        f4 v[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) v[k] = __builtin_nontemporal_load(q + 64 * k);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float x = v[k][j];
+                const bool ok = x == x;
+                m[k][j] = ok ? fmaxf(m[k][j], x) : m[k][j];
+                s[k][j] += (double)(ok ? x : 0.f);
+                n[k][j] += ok ? 1u : 0u;
+            }
+        q += sz4;
+    }
+    const int64_t o = a.slices == 1 ? 0 : (int64_t)blockIdx.y * a.nx * a.ny;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int64_t p = (qb + 64 * k + lane) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (a.slices == 1) {
+                if (a.mip) a.mip[p + j] = n[k][j] ? m[k][j] : qnan();
+                if (a.mom0) a.mom0[p + j] = n[k][j] ? s[k][j] : (double)qnan();
+                if (a.nvalid) a.nvalid[p + j] = n[k][j];
+            } else {
+                a.p_max[o + p + j] = m[k][j];
+                a.p_sum[o + p + j] = s[k][j];
+                a.p_cnt[o + p + j] = n[k][j];
+            }
         }
     }
 }
@@ -253,15 +320,27 @@ int cube_project(const float *ptr, const int64_t *dims, float *mip, double *mom0
         e = hipGetLastError();
         return e == hipSuccess ? CUBE_OK : hip_fail(e, "projection launch");
     }
-    // Quads when every row start is 16-byte aligned.
+    // Quads when every row start is 16-byte aligned; whole-image quads when,
+    // in addition, the rows follow each other in memory.
     const bool quad = (b.nx % 4 == 0) && ((uintptr_t)b.ptr % 16 == 0) &&
                       (b.ny == 1 || a.sy % 4 == 0) && (b.nz == 1 || a.sz % 4 == 0);
+    const bool rows = quad && (b.ny == 1 || a.sy == b.nx);
     const int V = quad ? 4 : 1;
     a.units = npix / V;
-    // Slices of the channel axis until about 16 wavefronts per CU are busy,
-    // each slice keeping at least 64 channels.
-    const int64_t waves = (a.units + 63) / 64;
-    const int64_t want = (int64_t)cu_count() * 16;
+    // Quads per lane on the fast path: the most that still leaves about four
+    // wavefronts per CU (each holds Q * 16 pixels of state in registers).
+    const int64_t cus = cu_count();
+    int Q = 1;
+    if (rows) {
+        Q = 4;
+        if ((a.units + 64 * 16 - 1) / (64 * 16) >= 4 * cus) Q = 16;
+        else if ((a.units + 64 * 8 - 1) / (64 * 8) >= 4 * cus) Q = 8;
+    }
+    // Slices of the channel axis until enough wavefronts are busy (16 per CU
+    // on the general path, 4 on the fast path), each slice keeping at least
+    // 64 channels.
+    const int64_t waves = (a.units + 64 * Q - 1) / (64 * Q);
+    const int64_t want = cus * (rows ? 4 : 16);
     int64_t slices = waves >= want ? 1 : (want + waves - 1) / waves;
     slices = std::min<int64_t>(slices, std::max<int64_t>(1, b.nz / 64));
     slices = std::min<int64_t>(slices, 64);
@@ -275,11 +354,34 @@ int cube_project(const float *ptr, const int64_t *dims, float *mip, double *mom0
         a.p_max = (float *)((char *)scr + per * 8);
         a.p_cnt = (uint32_t *)((char *)scr + per * 12);
     }
-    const dim3 grid((unsigned)((a.units + PROJ_THREADS - 1) / PROJ_THREADS), (unsigned)a.slices);
-    if (quad)
-        hipLaunchKernelGGL(k_project<4>, grid, dim3(PROJ_THREADS), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_project<1>, grid, dim3(PROJ_THREADS), 0, s, a);
+    // Whole wavefronts of the fast path first, then every remaining unit on
+    // the general kernel (all of them when the fast path does not apply).
+    int64_t done = 0;
+    if (rows) {
+        const int64_t full = a.units / (64 * Q);
+        done = full * 64 * Q;
+        if (full) {
+            a.u0 = done;
+            const dim3 grid((unsigned)((full * 64 + PROJ_THREADS - 1) / PROJ_THREADS),
+                            (unsigned)a.slices);
+            if (Q == 16)
+                hipLaunchKernelGGL(k_project_quads<16>, grid, dim3(PROJ_THREADS), 0, s, a);
+            else if (Q == 8)
+                hipLaunchKernelGGL(k_project_quads<8>, grid, dim3(PROJ_THREADS), 0, s, a);
+            else
+                hipLaunchKernelGGL(k_project_quads<4>, grid, dim3(PROJ_THREADS), 0, s, a);
+            if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "projection launch");
+        }
+    }
+    if (done < a.units) {
+        a.u0 = done;
+        const dim3 grid((unsigned)((a.units - done + PROJ_THREADS - 1) / PROJ_THREADS),
+                        (unsigned)a.slices);
+        if (quad)
+            hipLaunchKernelGGL(k_project<4>, grid, dim3(PROJ_THREADS), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_project<1>, grid, dim3(PROJ_THREADS), 0, s, a);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "projection launch");
     if (a.slices > 1) {
         hipLaunchKernelGGL(k_project_merge, dim3((unsigned)((npix + PROJ_THREADS - 1) / PROJ_THREADS)),

@@ -44,8 +44,13 @@ def cube_of(shape, seed, nan_frac=0.02):
     return synth.cube_tensor(r, seed, device="cuda")
 
 
+# Shapes (z, y, x) that reach every launch form: the whole-image quad path
+# with 4, 8 and 16 quads per lane, with and without a general-kernel tail and
+# channel slices; the row-wise kernel with quads and single pixels.
 @pytest.mark.parametrize("shape", [(128, 64, 64), (37, 41, 203), (5, 3, 4), (1, 1, 1),
-                                   (2000, 8, 16), (700, 5, 33), (64, 256, 256)])
+                                   (2000, 8, 16), (700, 5, 33), (64, 256, 256),
+                                   (50, 33, 260), (512, 16, 64), (8, 1024, 2048),
+                                   (4, 2049, 2048)])
 def test_project_shapes(cs, shape):
     t = cube_of(shape, 7 + shape[0])
     compare(cs.project(t), t.cpu().numpy(), f"shape {shape}")
