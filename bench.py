@@ -13,10 +13,16 @@ The JSON line carries:
               divided by its average launch duration, measured with HIP events
               on the launch stream, against the 8 TB/s HBM peak;
   cpu_baseline the oracle (single thread) on a bounded sample of the cube;
-  extra       two-pass [min, max] timings, stats-only and histogram-only
-              kernel timings, and the parity of the timed result.
+  p50_ms/p99_ms query latency of the continuous-batching server replaying a
+              seeded Poisson query mix over 12 resident cubes (about 201 GiB);
+  extra       two-pass [min, max], stats-only and histogram-only timings; the
+              64-cube batch (graph replay vs plain launches); selection and
+              median; projection maps; out-of-core queries from host memory;
+              the 128 GiB precision-stress cube; the serving replay (plain vs
+              served); the launch shapes used; parity checks of each.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       [--tune table|run|off] [--tune-save PATH] [--only-fused] [--no-...]
 """
 from __future__ import annotations
 
@@ -173,7 +179,7 @@ def bench_batch64(cs, synth, torch, dev, steps: int):
             "max_std_rel_diff_batched_vs_plain": worst}
 
 
-def bench_stress(cs, synth, torch, dev, steps: int):
+def bench_stress(cs, synth, torch, dev, steps: int, tune: bool = False):
     """The precision-stress cube at full size (4096 x 4096 x 2048, 128 GiB,
     offset 1e4): fused pass throughput over [min, max] with 4096 bins, and
     the moments of the three accumulation modes side by side (the oracle
@@ -197,6 +203,10 @@ def bench_stress(cs, synth, torch, dev, steps: int):
     out = torch.zeros(64, dtype=torch.uint8, device=dev)
     cnt = torch.zeros(nb + 3, dtype=torch.int64, device=dev)
     lo, hi = st.min, st.max
+    tuned = None
+    if tune:
+        tuned = cs.cube_autotune(cube.data_ptr(), dims, cs.CUBE_Q_FUSED, lo, hi, nb, reps=2)
+        log(f"autotune (stress fused): {tuned['best']}")
     _, ms = time_launches(lambda: cs.cube_stats_hist_async(ptr, dims, lo, hi, nb, out.data_ptr(),
                                                            cnt.data_ptr(), sp),
                           stream, steps, 2)
@@ -205,6 +215,7 @@ def bench_stress(cs, synth, torch, dev, steps: int):
     del cube
     torch.cuda.empty_cache()
     return {"voxels": r.n, "nbins": nb, "fused_ms": ms, "voxels_per_s": r.n / (ms * 1e-3),
+            "autotune": tuned,
             "pct_hbm_peak": 100.0 * 4 * r.n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bin0_fraction_of_valid": float(c[0]) / max(1, st.n_valid),
             "counts_sum_equals_n_total": int(c.sum()) == r.n,
@@ -449,8 +460,6 @@ def main() -> int:
                             ("hist", cs.CUBE_Q_HIST)):
             tuned[kname] = cs.cube_autotune(cube.data_ptr(), dims, kind, lo, hi, nbins, reps=4)
             log(f"autotune ({kname}): {tuned[kname]['best']}")
-    if args.tune_save:
-        cs.cube_tune_save(args.tune_save)
 
     stream = torch.cuda.Stream(device=dev)
     out = torch.zeros(64, dtype=torch.uint8, device=dev)
@@ -564,7 +573,7 @@ def main() -> int:
         del cube
         cube = None
         torch.cuda.empty_cache()
-        extra["stress128g"] = bench_stress(cs, synth, torch, dev, 10)
+        extra["stress128g"] = bench_stress(cs, synth, torch, dev, 10, tune=mode == "run")
         log(f"stress128g: fused {extra['stress128g']['fused_ms']:.3f} ms "
             f"({extra['stress128g']['pct_hbm_peak']:.1f} % of HBM peak)")
     if not args.only_fused and not args.no_serve:
@@ -576,6 +585,8 @@ def main() -> int:
         result["p99_ms"] = sv["served"]["p99_ms"]
         log(f"serve: plain p50/p99 {sv['plain']['p50_ms']:.2f}/{sv['plain']['p99_ms']:.2f} ms, "
             f"served {sv['served']['p50_ms']:.2f}/{sv['served']['p99_ms']:.2f} ms")
+    if args.tune_save:
+        cs.cube_tune_save(args.tune_save)
     print(json.dumps(result), flush=True)
     return 0 if all(parity.values()) else 1
 
