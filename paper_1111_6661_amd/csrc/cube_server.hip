@@ -135,9 +135,13 @@ void worker_loop(cube_server *srv)
             Slot &sl = srv->slots[s];
             if (!sl.busy) continue;
             const double t = now_s();
+            // A query already completed may also have been collected (and
+            // erased) by cube_server_wait: look entries up, never create.
             if (srv->mode == 0) {
                 for (size_t k = 0; k < sl.ids.size(); ++k) {
-                    Entry &e = srv->entries[sl.ids[k]];
+                    auto it = srv->entries.find(sl.ids[k]);
+                    if (it == srv->entries.end()) continue;
+                    Entry &e = it->second;
                     if (e.state == 1 && cube_batch_query_done(sl.batch, (int32_t)k)) {
                         e.state = 2;
                         e.t_done = t;
@@ -149,7 +153,9 @@ void worker_loop(cube_server *srv)
             }
             if (hipEventQuery(sl.done) != hipSuccess) continue;
             for (uint64_t id : sl.ids) {
-                Entry &e = srv->entries[id];
+                auto it = srv->entries.find(id);
+                if (it == srv->entries.end()) continue;
+                Entry &e = it->second;
                 if (e.state == 2) continue;
                 e.state = 2;
                 e.t_done = t;

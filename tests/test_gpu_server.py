@@ -134,3 +134,27 @@ def test_server_rejects_bad_queries(cs, cubes):
     with pytest.raises(cs.CubeError):
         srv.wait(12345, timeout_s=0.01)
     srv.close()
+
+
+def test_early_completions_counted_once(cs):
+    """Small queries finish (by their completion flags) and are collected by
+    wait() long before the large query of the same batch: each latency is
+    recorded once, and collected ids are never brought back."""
+    big = torch.randn(1 << 28, device="cuda")
+    small = [torch.randn(4096, device="cuda") for _ in range(7)]
+    out = torch.zeros((8, 64), dtype=torch.uint8, device="cuda")
+    srv = cs.Server(cs.CUBE_SERVE_BATCHED, slots=1, max_batch=8, tile_voxels=1 << 16)
+    for rep in range(3):
+        qs = [cs.make_query(*cs.box_of(t), cs.CUBE_Q_STATS, 0, 0.0, 0.0, out[i].data_ptr())
+              for i, t in enumerate([big] + small)]
+        ids = [srv.submit(q) for q in qs]
+        for i in ids[1:] + ids[:1]:      # the small ones first
+            assert srv.wait(i, timeout_s=60) >= 0
+        time.sleep(0.05)                 # let the worker see the batch's event
+        p50, p99, n = srv.latency(reset=True)
+        assert n == len(qs), (rep, n)
+    srv.close()
+    torch.cuda.synchronize()
+    for i, t in enumerate(small):
+        st = cs.Stats.from_bytes(out[i + 1].cpu().numpy().tobytes())
+        assert st.n_valid == 4096 and st.max == float(t.max())
