@@ -283,9 +283,9 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
         copies_req = ts.copies;
         blocks = (long long)cu_count() * ts.blocks_per_cu;
     }
-    // Boxes under 2^26 voxels default to 256 threads: their launches are
-    // short enough that per-block costs dominate (below).
-    const bool small = b.n < ((uint64_t)1 << 26);
+    // Histogram passes over boxes under 2^25 voxels default to 256 threads:
+    // their launches are short enough that per-block costs dominate (below).
+    const bool small = b.n < ((uint64_t)1 << 25);
     if (threads != 256 && threads != 512 && threads != 1024)
         threads = (hist_kind_req && !small) ? 1024 : 256;
     p->threads = threads;
@@ -321,12 +321,20 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
         blocks = (long long)((b.n + per_block_min - 1) / per_block_min);
         // Every block adds a fixed cost at the end of the pass (its ticket
         // atomic on one address, its release fence, its records for the
-        // final merge; about 9-30 ns each, measured), while the streaming
+        // final merge, and for histograms one flush of every bin; measured
+        // at 9-30 ns per block for the first three), while the streaming
         // time falls as n / blocks: the sum is least near sqrt(n) blocks.
-        // sqrt(n) / 16 matched the fastest block count measured from 2^16
-        // to 2^24 voxels and reaches the CU cap from 2^28 on.
-        const long long root = (long long)sqrt((double)b.n) / 16;
-        if (blocks > root) blocks = root < 1 ? 1 : root;
+        // Measured on boxes of 2^16 to 2^30 voxels, the fastest counts were
+        // about sqrt(n) / 16, up to one block per CU for histogram passes
+        // (each block flushes its whole LDS histogram) and two for the
+        // statistics pass; the largest boxes keep the CU cap (or the tuned
+        // shape).
+        if (b.n < ((uint64_t)1 << 31)) {
+            long long root = (long long)sqrt((double)b.n) / 16;
+            const long long mid = (long long)cu_count() * (hist_kind_req ? 1 : 2);
+            if (root > mid) root = mid;
+            if (blocks > root) blocks = root < 1 ? 1 : root;
+        }
         if (blocks > cap) blocks = cap;
     }
     // Per-block LDS counters are 32-bit: keep every block under 2^31 voxels.
