@@ -106,7 +106,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
             if (tid == 0) {
                 unsigned int spins = 0;
                 s_flag = 1u;
-                while (__hip_atomic_load(&st->ready, __ATOMIC_ACQUIRE,
+                // Relaxed polls, then one acquire fence once the flag is up.
+                while (__hip_atomic_load(&st->ready, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT) == 0u) {
                     __builtin_amdgcn_s_sleep(8);
                     if (++spins > a.spin_limit) {
@@ -115,7 +116,10 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                         break;
                     }
                 }
-                if (s_flag) s_range = st->range;
+                if (s_flag) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    s_range = st->range;
+                }
             }
             __syncthreads();
             skip = s_flag == 0u;
@@ -149,17 +153,10 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         if (hist) hist_flush(lds, it.nbins, a.copies_log2, acc);
 
         // Completion of the query's phase: the last tile merges.  One
-        // release fence per block, after the barrier (see k_pass).
-        __syncthreads();
+        // release fence per block (see last_to_arrive).
         const int ntiles = tile.phase == 1 ? it.ntiles1 : it.ntiles2;
-        if (tid == 0) {
-            __threadfence();
-            unsigned int *done = tile.phase == 1 ? &st->done1 : &st->done2;
-            s_flag = atomicAdd(done, 1u) == (unsigned int)(ntiles - 1);
-        }
-        __syncthreads();
-        if (s_flag) {
-            __threadfence();
+        if (last_to_arrive(tile.phase == 1 ? &st->done1 : &st->done2, (unsigned int)ntiles,
+                           &s_flag)) {
             const int n_recs = ntiles * nw;
             unsigned long long nv, below, above;
             if (stats) {
@@ -182,8 +179,9 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                 if (tile.phase == 1) {
                     st->done1 = 0u;
                     if (it.kind == BQ_MINMAX) {
+                        // A release store: it orders the range (and, over
+                        // the barrier, every thread's writes) before the flag.
                         finished = false;
-                        __threadfence();
                         __hip_atomic_store(&st->ready, 1u, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     }
@@ -194,8 +192,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                     st->ready = 0u;
                 }
                 if (finished && a.done_flags) {
-                    // The query's outputs are complete: tell the host.
-                    __threadfence_system();
+                    // The query's outputs are complete: tell the host (a
+                    // system-scope release store orders the outputs first).
                     __hip_atomic_store(&a.done_flags[tile.item], a.gen, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_SYSTEM);
                 }

@@ -328,6 +328,28 @@ __device__ __forceinline__ void lds_zero(unsigned int *lds, int nbins, int copie
     __syncthreads();
 }
 
+// The "last block merges" ticket.  Called by every thread of the block after
+// its writes.  After a barrier, thread 0 issues one agent-scope release fence
+// (fences are cumulative: it covers every thread's writes ordered before it
+// by the barrier; on gfx950 it writes back the L2), takes a ticket and, if it
+// is the last of `total`, one agent-scope acquire fence (an L2 and L1
+// invalidate) before the barrier that lets the block read the others' writes.
+// A full __threadfence() is both, and one in every thread costs a write-back
+// per wavefront.  Returns the same answer to every thread.
+__device__ __forceinline__ bool last_to_arrive(unsigned int *ticket, unsigned int total,
+                                               unsigned int *s_shared)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const bool last = atomicAdd(ticket, 1u) == total - 1u;
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_shared = last ? 1u : 0u;
+    }
+    __syncthreads();
+    return *s_shared != 0u;
+}
+
 // Scan the work units [u0, u1) of a box (segments of rows, see Geom).
 template <bool STATS, int HIST, int ACC, int U>
 __device__ __forceinline__ void scan_units(const Geom &g, long long u0, long long u1, Lane &L,

@@ -217,14 +217,7 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
         if (sum) atomicAdd(&a.acc[b], (unsigned long long)sum);
     }
     if (p == 0 && lane == 0 && valid) atomicAdd(&a.st->n_valid, valid);
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();  // one release per block, after the barrier
-        s_last = (atomicAdd(a.ticket, 1u) == (unsigned int)(gridDim.x - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    if (!last_to_arrive(a.ticket, gridDim.x, &s_last)) return;
 
     // Last block: find the bin holding the rank (counts in bin order), then
     // return the accumulators to zero.
@@ -298,14 +291,7 @@ __global__ void __launch_bounds__(1024) k_select_next(SelectArgs a)
         m = o < m ? o : m;
     }
     if ((tid & 63) == 0 && m != 0xffffffffu) atomicMin(&a.st->next_key, m);
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        s_last = (atomicAdd(a.ticket, 1u) == (unsigned int)(gridDim.x - 1));
-    }
-    __syncthreads();
-    if (!s_last || tid != 0) return;
-    __threadfence();
+    if (!last_to_arrive(a.ticket, gridDim.x, &s_last) || tid != 0) return;
     a.st->value_next = key_value(__hip_atomic_load(&a.st->next_key, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT));
     *a.ticket = 0u;
