@@ -185,7 +185,9 @@ CUBE_API int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copie
  * middle one for odd n_valid, the FP64 mean of the two middle ones for even
  * n_valid (and n_valid in *n_valid when not NULL); CUBE_EINVAL when no voxel
  * is valid.  Three histogram passes over 32-bit order keys (12 + 12 + 8
- * bits), with the bucket choice made on the device; for an even count the
+ * bits), with the bucket choice made on the device; the second pass copies
+ * the first pass's bucket out when it fits (64 MiB of device memory kept by
+ * the library), and the third then reads only that; for an even count the
  * upper middle comes from the same passes or from at most one more
  * (minimum) pass.  Synchronous, on the default stream; results are exact.
  */

@@ -35,6 +35,8 @@ struct SelectState {
     unsigned int need_next;      // ...which the last histogram did not hold
     unsigned int next_key;       // smallest key above the selected one (min)
     float value_next;            // the voxel of the next rank
+    unsigned int collect;        // pass 1 copies the first pass's bucket out
+    unsigned int overflow;       // ...and a block's region overflowed
 };
 
 struct SelectArgs {
@@ -44,6 +46,9 @@ struct SelectArgs {
     unsigned long long *acc;     // 4096 accumulators, zero between passes
     unsigned int *ticket;
     float *out;                  // optional device copy of the result
+    float *cand;                 // per-block candidate regions, cand_cap floats each
+    unsigned int *cand_n;        // voxels each block copied (pass 1)
+    unsigned int cand_cap;
 };
 
 // Pass p histograms key bits [shift, shift + width): widths 12, 12, 8.
@@ -69,9 +74,15 @@ struct SelCtx {
     unsigned int bin_mask;
     int shift, base;    // LDS addressing as in Hist
     unsigned int *lds;
+    unsigned int *s_cnt;     // candidates this block copied (LDS counter)
+    float *cand;             // this block's candidate region
+    unsigned int cand_cap;
 };
 
-template <int NV>
+// With COLLECT, every voxel that matches the prefix is also copied to the
+// block's candidate region: one LDS atomic per wavefront step that has any
+// match, each matching lane at its rank among the matches (mbcnt).
+template <int NV, bool COLLECT = false>
 __device__ __forceinline__ void select_step(const float (&x)[NV], unsigned long long &valid,
                                             const SelCtx &c)
 {
@@ -87,6 +98,18 @@ __device__ __forceinline__ void select_step(const float (&x)[NV], unsigned long 
         const int b = (int)((k >> c.bin_shift) & c.bin_mask);
         const int bb = keep_or_minus1(b, inr);
         atomicAdd((unsigned int *)((char *)c.lds + ((bb << c.shift) + c.base)), 1u);
+        if (COLLECT && inr) {  // wavefront-uniform
+            const int lane = threadIdx.x & 63;
+            unsigned int base = 0;
+            if (lane == 0) base = atomicAdd(c.s_cnt, (unsigned int)__popcll(inr));
+            base = __shfl(base, 0);
+            if ((inr >> lane) & 1ull) {
+                const unsigned int i =
+                    base + __builtin_amdgcn_mbcnt_hi((unsigned int)(inr >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned int)inr, 0u));
+                if (i < c.cand_cap) c.cand[i] = v;
+            }
+        }
     }
     asm("" : "+s"(cv));
     valid += cv;
@@ -158,14 +181,15 @@ __device__ __forceinline__ void scan_box(const Geom &g, Step &step)
     }
 }
 
-// Counting step of a select pass.
+// Counting step of a select pass (and, with COLLECT, copying).
+template <bool COLLECT>
 struct CountStep {
     SelCtx c;
     unsigned long long valid;
     template <int NV>
     __device__ __forceinline__ void operator()(const float (&x)[NV])
     {
-        select_step<NV>(x, valid, c);
+        select_step<NV, COLLECT>(x, valid, c);
     }
 };
 
@@ -186,13 +210,13 @@ struct NextStep {
 __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
 {
     extern __shared__ unsigned int lds[];
-    __shared__ unsigned int s_last;
+    __shared__ unsigned int s_last, s_cnt;
     __shared__ unsigned long long s_part[1024];
     const int tid = threadIdx.x, B = blockDim.x;
     const int p = a.pass;
     const int width = sel_width(p);
     const int nbins = 1 << width;
-    CountStep cs;
+    CountStep<false> cs;
     SelCtx &c = cs.c;
     const int top = sel_shift(p) + width;   // first key bit above this pass's bins
     c.hi_mask = p == 0 ? 0u : (0xffffffffu << top);
@@ -203,9 +227,36 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
     c.shift = a.copies_log2 + 2;
     c.base = (C + (tid & 63 & (C - 1))) * 4;
     c.lds = lds;
+    c.s_cnt = &s_cnt;
+    c.cand = a.cand + (size_t)blockIdx.x * a.cand_cap;
+    c.cand_cap = a.cand_cap;
+    if (tid == 0) s_cnt = 0u;
     lds_zero(lds, nbins, a.copies_log2);
     cs.valid = 0;
-    scan_box(a.g, cs);
+    const bool collect = p == 1 && a.st->collect;
+    const bool from_cand = p == 2 && a.st->collect && !a.st->overflow;
+    if (collect) {
+        CountStep<true> cc;
+        cc.c = c;
+        cc.valid = 0;
+        scan_box(a.g, cc);
+        __syncthreads();
+        if (tid == 0) {
+            a.cand_n[blockIdx.x] = min(s_cnt, a.cand_cap);
+            if (s_cnt > a.cand_cap) atomicOr(&a.st->overflow, 1u);
+        }
+    } else if (from_cand) {
+        // The third pass over this block's candidates only (all valid, all
+        // in the first pass's bucket), in wavefront-uniform steps.
+        const unsigned int n = a.cand_n[blockIdx.x];
+        for (unsigned int i0 = 0; i0 < n; i0 += (unsigned int)B) {
+            const unsigned int i = i0 + (unsigned int)tid;
+            float xv[1] = {i < n ? c.cand[i] : qnan()};
+            select_step<1>(xv, cs.valid, c);
+        }
+    } else {
+        scan_box(a.g, cs);
+    }
     const unsigned long long valid = cs.valid;
     const int lane = tid & 63;
     // Flush bins (slot b + 1 holds bin b); the valid count goes with the
@@ -246,6 +297,11 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
             const unsigned int up = st.prefix << width;
             st.prefix = up | (unsigned int)b;
             st.rank -= before;
+            // The second pass copies this bucket out when it fits the
+            // candidate regions; the third then reads only those.
+            if (p == 0)
+                st.collect = a.cand && a.acc[b] <= (unsigned long long)a.cand_cap * gridDim.x
+                                 ? 1u : 0u;
             if (p == 2) {
                 st.value = key_value(st.prefix);
                 if (a.out) *a.out = st.value;
@@ -303,11 +359,17 @@ using namespace cube;
 
 namespace {
 
+// Candidate regions: 2^15 floats per block (64 MiB over 512 blocks).
+constexpr unsigned int CAND_PER_BLOCK = 1u << 15;
+
 struct SelectWorkspace {
     SelectState *st = nullptr;
     unsigned long long *acc = nullptr;
     unsigned int *ticket = nullptr;
     SelectState *h_st = nullptr;  // pinned
+    float *cand = nullptr;
+    unsigned int *cand_n = nullptr;
+    int cand_blocks = 0;
 };
 
 std::mutex g_smu;
@@ -337,7 +399,8 @@ int select_ws(SelectWorkspace **out)
 }
 
 // Three passes on the default stream (and, for the median of an even count,
-// at most one more); the result is read back.  With rank_mode 1 the rank is
+// at most one more); the result is read back.  The third pass reads only the
+// candidates the second copied out, unless they did not fit.  With rank_mode 1 the rank is
 // the lower middle of the valid voxels and, for an even count, *next is the
 // upper middle.
 int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64_t *n_valid,
@@ -370,6 +433,20 @@ int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64
     a.st = w->st;
     a.acc = w->acc;
     a.ticket = w->ticket;
+    if (w->cand_blocks < blocks) {
+        hipFree(w->cand);
+        hipFree(w->cand_n);
+        w->cand = nullptr;
+        w->cand_n = nullptr;
+        w->cand_blocks = 0;
+        if ((e = hipMalloc(&w->cand, (size_t)blocks * CAND_PER_BLOCK * 4)) != hipSuccess ||
+            (e = hipMalloc(&w->cand_n, (size_t)blocks * 4)) != hipSuccess)
+            return hip_fail(e, "select candidates");
+        w->cand_blocks = blocks;
+    }
+    a.cand = w->cand;
+    a.cand_n = w->cand_n;
+    a.cand_cap = CAND_PER_BLOCK;
     for (int p = 0; p < 3; ++p) {
         a.pass = p;
         const int nb = 1 << sel_width(p);

@@ -89,3 +89,27 @@ def test_median_even_count_upper_middle(cs):
         m, nv = cs.median(t)
         assert nv == int((~np.isnan(a)).sum())
         assert m == oracle.median(a), (a[:8], m, oracle.median(a))
+
+
+def test_select_candidate_paths(cs):
+    """The third pass reads the candidates the second copied out (a small
+    first-pass bucket), the whole cube when the bucket is too large to copy,
+    and the whole cube again when one block's region overflowed."""
+    rng = np.random.default_rng(17)
+    # a bucket of 2^25 equal voxels: larger than every candidate region together
+    many = np.full(1 << 25, 1.5, np.float32)
+    many[::7] = rng.standard_normal(many[::7].size).astype(np.float32)
+    # 10M equal voxels at the front: about 10M in the bucket (fits in total)
+    # but about 39K of them in each of the first blocks (more than a region)
+    skew = rng.standard_normal(20_000_000).astype(np.float32)
+    skew[:10_000_000] = 0.25
+    # small buckets everywhere: the candidate path
+    spread = (rng.standard_normal(5_000_003) * 100).astype(np.float32)
+    spread[rng.random(spread.size) < 0.01] = np.nan
+    for a in (many, skew, spread):
+        t = torch.from_numpy(a).cuda()
+        n = int((~np.isnan(a)).sum())
+        for k in (0, n // 3, (n - 1) // 2, n - 1):
+            assert same_f32(cs.select(t, k), oracle.select(a, k)), (a.size, k)
+        m, nv = cs.median(t)
+        assert nv == n and m == oracle.median(a), a.size
