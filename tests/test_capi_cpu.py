@@ -100,3 +100,32 @@ def test_binding_has_no_cpu_fallback():
         cs.stats(torch.zeros(8))
     src = open(os.path.join(ROOT, "paper_1111_6661_amd", "__init__.py")).read()
     assert "import oracle" not in src and "from oracle" not in src
+
+
+def test_tuning_table_round_trip(tmp_path):
+    """The shipped gfx950 table loads; save writes what load reads back; bad
+    files are rejected without touching the table (no GPU call involved)."""
+    table = os.path.join(ROOT, "paper_1111_6661_amd", "tuning", "gfx950.json")
+    cs.cube_tune_clear()
+    try:
+        n = cs.cube_tune_load(table)
+        assert n >= 3
+        out = tmp_path / "t.json"
+        cs.cube_tune_save(str(out))
+        cs.cube_tune_clear()
+        assert cs.cube_tune_load(str(out)) == n
+        lines = sorted(l.strip().rstrip(",") for l in open(out) if '"kind"' in l)
+        want = sorted(l.strip().rstrip(",") for l in open(table) if '"kind"' in l)
+        assert [l.split('"ms"')[0] for l in lines] == [l.split('"ms"')[0] for l in want]
+        bad_arch = tmp_path / "arch.json"
+        bad_arch.write_text(open(table).read().replace("gfx950", "gfx942"))
+        with pytest.raises(cs.CubeError):
+            cs.cube_tune_load(str(bad_arch))
+        bad_entry = tmp_path / "entry.json"
+        bad_entry.write_text(open(table).read().replace('"unroll": 4', '"unroll": 3', 1))
+        with pytest.raises(cs.CubeError):
+            cs.cube_tune_load(str(bad_entry))
+        with pytest.raises(cs.CubeError):
+            cs.cube_tune_load(str(tmp_path / "missing.json"))
+    finally:
+        cs.cube_tune_clear()

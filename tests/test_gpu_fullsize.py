@@ -22,12 +22,17 @@ torch = pytest.importorskip("torch")
 
 @pytest.fixture(scope="module")
 def cs():
+    """The library in the launch configuration bench.py times: the shipped
+    gfx950 tuning table loaded, no explicit shape."""
     import paper_1111_6661_amd as cs
     assert torch.cuda.is_available()
     cs.load()
     cs.cube_set_launch(0, 0, 0, 0)
     cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
-    return cs
+    table = os.path.join(os.path.dirname(cs.__file__), "tuning", "gfx950.json")
+    assert cs.cube_tune_load(table) >= 1
+    yield cs
+    cs.cube_tune_clear()
 
 
 def _host_copy(t):

@@ -272,3 +272,23 @@ def test_accum_modes_run_and_rank(cs):
     assert errs[cs.CUBE_ACCUM_FP64MERGE] <= 1e-6
     assert errs[cs.CUBE_ACCUM_NAIVE32] > errs[cs.CUBE_ACCUM_FP64MERGE]
     print("std rel err naive/kahan32/fp64merge:", errs)
+
+
+def test_autotune_then_planner_uses_it(cs, tiny):
+    """The autotuner times shapes on the caller's data, reports the best, and
+    later calls without an explicit shape use it; counts stay bit-exact."""
+    t, host = tiny
+    ptr, d = cs.box_of(t)
+    lo, hi, nb = -3.0, 40.0, 256
+    want = oracle.hist(host, lo, hi, nb)
+    cs.cube_tune_clear()
+    try:
+        rep = cs.cube_autotune(ptr, d, cs.CUBE_Q_FUSED, lo, hi, nb, reps=1)
+        assert rep["candidates"] > 1 and rep["best"]["ms"] <= rep["worst"]["ms"]
+        st, counts = cs.stats_hist(t, lo, hi, nb)
+        assert_counts_match(counts, want, "tuned shape")
+        assert_stats_match(st, oracle.stats(host), "tuned shape")
+        with pytest.raises(cs.CubeError):
+            cs.cube_autotune(ptr, d, cs.CUBE_Q_MINMAX, lo, hi, nb, reps=1)
+    finally:
+        cs.cube_tune_clear()
