@@ -176,6 +176,9 @@ def bench_batch64(cs, synth, torch, dev, steps: int):
             "batched_graph_ms": ev_b, "plain_ms": ev_p,
             "batched_voxels_per_s": nvox / (ev_b * 1e-3), "plain_voxels_per_s": nvox / (ev_p * 1e-3),
             "speedup": ev_p / ev_b, "counts_and_extrema_equal": counts_equal,
+            # two reads of every voxel (statistics, then the [min, max] histogram)
+            "batched_gbs": 8 * nvox / (ev_b * 1e-3) / 1e9,
+            "batched_frac_hbm_peak": 8 * nvox / (ev_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "max_std_rel_diff_batched_vs_plain": worst}
 
 

@@ -292,3 +292,43 @@ def test_autotune_then_planner_uses_it(cs, tiny):
             cs.cube_autotune(ptr, d, cs.CUBE_Q_MINMAX, lo, hi, nb, reps=1)
     finally:
         cs.cube_tune_clear()
+
+
+def test_concurrent_calls_on_streams(cs, tiny):
+    """Single-box calls from several host threads at once, each on its own
+    stream (each stream has its own workspace) and through the synchronous
+    entry points (which share the default stream's): every result equals the
+    one computed alone."""
+    import threading
+    t, host = tiny
+    lo, hi, nb = -3.0, 40.0, 256
+    ref_st = oracle.stats(host)
+    ref_c = oracle.hist(host, lo, hi, nb)
+    errors = []
+
+    def worker(k):
+        try:
+            s = torch.cuda.Stream()
+            out = torch.zeros(64, dtype=torch.uint8, device="cuda")
+            cnt = torch.zeros(nb + 3, dtype=torch.int64, device="cuda")
+            ptr, d = cs.box_of(t)
+            for _ in range(20):
+                if k % 2:
+                    cs.cube_stats_hist_async(ptr, d, lo, hi, nb, out.data_ptr(), cnt.data_ptr(),
+                                             s.cuda_stream)
+                    s.synchronize()
+                    st = cs.Stats.from_bytes(out.cpu().numpy().tobytes())
+                    c = cnt.cpu().numpy().view(np.uint64)
+                else:
+                    st, c = cs.stats_hist(t, lo, hi, nb)
+                assert_stats_match(st, ref_st, f"thread {k}")
+                assert_counts_match(c, ref_c, f"thread {k}")
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(6)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errors, errors[0]
