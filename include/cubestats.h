@@ -289,10 +289,12 @@ CUBE_API int cube_batch_set_order(cube_batch_t *b, int32_t order);
  * no GPU call.  Valid after cube_batch_enqueue and cube_batch_relaunch (a
  * graph replay repeats the generation it captured, so use the stream). */
 CUBE_API int cube_batch_query_done(cube_batch_t *b, int32_t i);
-/* Launch the last enqueued work list again (no host work, no copies). */
+/* Launch the last enqueued work list again (no host work, no copies).
+ * Launches of one batch object are ordered: one on another stream than the
+ * previous launch waits, on the device, for that launch to finish. */
 CUBE_API int cube_batch_relaunch(cube_batch_t *b, void *stream);
 /* Same as cube_batch_relaunch through a captured HIP graph: the first call
- * per stream captures the launch, later calls replay it. */
+ * after an enqueue captures the launch, later calls replay it on any stream. */
 CUBE_API int cube_batch_graph_launch(cube_batch_t *b, void *stream);
 /* Wait for the batch and report whether every two-pass query completed
  * (CUBE_EDEVICE if a query's bounded wait for its range expired). */

@@ -241,6 +241,7 @@ struct cube_batch {
     BatchTile *h_tiles = nullptr;   // pinned
     hipStream_t last_stream = nullptr;
     hipEvent_t staged = nullptr;    // the last work-list copy has been read
+    hipEvent_t launched = nullptr;  // recorded after every launch of the batch
     unsigned int *h_done = nullptr; // host-mapped per-query completion flags
     unsigned int *d_done = nullptr; // the same memory as the device sees it
     size_t cap_done = 0;
@@ -251,20 +252,22 @@ struct cube_batch {
     int threads = 512, blocks = 0;
     size_t lds = 0;
     long long tile_voxels = 1 << 20;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    hipStream_t graph_stream = nullptr;
+    hipGraph_t graph = nullptr;       // the launch, captured once per work list;
+    hipGraphExec_t graph_exec = nullptr;  // replayed on any stream
 };
 
 namespace {
 
 void drop_graph(cube_batch *b)
 {
+    if (!b->graph_exec && !b->graph) return;
+    // A replay may still be running: the last launch's event covers it
+    // (launches of a batch are ordered).
+    if (b->launched) hipEventSynchronize(b->launched);
     if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
     if (b->graph) hipGraphDestroy(b->graph);
     b->graph_exec = nullptr;
     b->graph = nullptr;
-    b->graph_stream = nullptr;
 }
 
 void free_buffers(cube_batch *b)
@@ -350,6 +353,24 @@ int ensure_done(cube_batch *b, size_t n)
     return CUBE_OK;
 }
 
+// Launches of one batch share its device state: a launch on another stream
+// than the previous one waits (on the device) for that one to finish.
+hipError_t order_after_previous(cube_batch *b, hipStream_t s)
+{
+    if (!b->launched) return hipSuccess;
+    return b->last_stream == s ? hipSuccess : hipStreamWaitEvent(s, b->launched, 0);
+}
+
+hipError_t mark_launched(cube_batch *b, hipStream_t s)
+{
+    hipError_t e;
+    if (!b->launched &&
+        (e = hipEventCreateWithFlags(&b->launched, hipEventDisableTiming)) != hipSuccess)
+        return e;
+    b->last_stream = s;
+    return hipEventRecord(b->launched, s);
+}
+
 int launch_batch(cube_batch *b, hipStream_t s)
 {
     // A new generation per launch: completion flags of earlier launches
@@ -358,10 +379,12 @@ int launch_batch(cube_batch *b, hipStream_t s)
     b->args.gen = b->gen;
     BatchArgs a = b->args;
     void *args[] = {&a};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&k_batch), dim3(b->blocks),
-                                   dim3(b->threads), args, b->lds, s);
+    hipError_t e = order_after_previous(b, s);
+    if (e != hipSuccess) return hip_fail(e, "batch ordering");
+    e = hipLaunchKernel(reinterpret_cast<const void *>(&k_batch), dim3(b->blocks),
+                        dim3(b->threads), args, b->lds, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
-    b->last_stream = s;
+    if ((e = mark_launched(b, s)) != hipSuccess) return hip_fail(e, "batch event");
     return CUBE_OK;
 }
 
@@ -386,6 +409,7 @@ void cube_batch_destroy(cube_batch_t *b)
         drop_graph(b);
         free_buffers(b);
         if (b->staged) hipEventDestroy(b->staged);
+        if (b->launched) hipEventDestroy(b->launched);
         if (b->h_done) hipHostFree(b->h_done);
     }
     delete b;
@@ -577,8 +601,7 @@ int cube_batch_graph_launch(cube_batch_t *b, void *stream)
     if (!b->have_work) return CUBE_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
-    if (!b->graph_exec || b->graph_stream != s) {
-        drop_graph(b);
+    if (!b->graph_exec) {
         // Capture on a private stream (a legacy default stream cannot be
         // captured), then replay the graph on the caller's stream.
         hipStream_t cap;
@@ -606,10 +629,10 @@ int cube_batch_graph_launch(cube_batch_t *b, void *stream)
         }
         b->graph = g;
         b->graph_exec = ge;
-        b->graph_stream = s;
     }
+    if ((e = order_after_previous(b, s)) != hipSuccess) return hip_fail(e, "batch ordering");
     if ((e = hipGraphLaunch(b->graph_exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
-    b->last_stream = s;
+    if ((e = mark_launched(b, s)) != hipSuccess) return hip_fail(e, "batch event");
     return CUBE_OK;
 }
 

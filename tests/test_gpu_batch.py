@@ -162,3 +162,33 @@ def test_query_done_flags_and_order(cs):
     with pytest.raises(cs.CubeError):
         b.set_order(7)
     b.close()
+
+
+def test_relaunch_across_streams_is_ordered(cs):
+    """Launches of one batch on different streams run one after another
+    (they share the batch's device state): every launch's outputs equal the
+    first launch's, with no host synchronisation between the launches."""
+    items = make_items(seed=21, n=10)
+    outs = Outputs(len(items), 512)
+    kinds = [cs.CUBE_Q_MINMAX, cs.CUBE_Q_FUSED, cs.CUBE_Q_STATS, cs.CUBE_Q_HIST]
+    qs = queries_for(cs, items, outs, kinds, [512, 64])
+    b = cs.Batch(tile_voxels=1 << 12)
+    s = [torch.cuda.Stream() for _ in range(3)]
+    b.enqueue(qs, s[0].cuda_stream)
+    b.check()
+    first_out, first_cnt = outs.out.clone(), outs.cnt.clone()
+    for rep in range(4):
+        outs.out.zero_()
+        outs.cnt.zero_()
+        torch.cuda.synchronize()
+        b.relaunch(s[1].cuda_stream)
+        b.graph_launch(s[2].cuda_stream)
+        b.relaunch(s[0].cuda_stream)
+        b.graph_launch(s[1].cuda_stream)
+        b.check()
+        torch.cuda.synchronize()
+        assert torch.equal(outs.out, first_out), rep
+        assert torch.equal(outs.cnt, first_cnt), rep
+    b.close()
+    for i, t in enumerate(items):
+        check_query(cs, outs, i, t, kinds[i % len(kinds)], [512, 64][i % 2])
