@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.parity import assert_counts_match, assert_stats_match
+from tests.parity import assert_counts_match, assert_stats_match, same_f32
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -192,3 +192,43 @@ def test_relaunch_across_streams_is_ordered(cs):
     b.close()
     for i, t in enumerate(items):
         check_query(cs, outs, i, t, kinds[i % len(kinds)], [512, 64][i % 2])
+
+
+def test_batch64_workload_precision(cs):
+    """The 64-cube batch workload: every item's batched result (FP64 merge of
+    compensated FP32 partials) against the oracle, and the same items through
+    the naive-FP32 and Kahan-FP32 modes of the single-box pass, whose errors
+    are reported beside it.  Only the production path is held to 1e-6."""
+    import synth
+    recs = synth.batch_item_recipes()
+    items = [synth.cube_tensor(r, synth.BASE_SEED + 2 + i, device="cuda")
+             for i, r in enumerate(recs)]
+    nb = synth.HIST_BINS["batch64"]
+    outs = Outputs(len(items), nb)
+    qs = [cs.make_query(*cs.box_of(t), cs.CUBE_Q_MINMAX, nb, 0.0, 0.0, outs.out[i].data_ptr(),
+                        outs.cnt[i].data_ptr()) for i, t in enumerate(items)]
+    b = cs.Batch(tile_voxels=1 << 18)
+    b.enqueue(qs)
+    b.check()
+    b.close()
+    worst = {"batched": 0.0, "naive32": 0.0, "kahan32": 0.0}
+    try:
+        for i, t in enumerate(items):
+            host = t.cpu().numpy()
+            ref = oracle.stats(host)
+            st = outs.stats(cs, i)
+            assert_stats_match(st, ref, f"batched item {i}")
+            assert_counts_match(outs.counts(i, nb), oracle.hist(host, ref.min, ref.max, nb),
+                                f"batched item {i}")
+            worst["batched"] = max(worst["batched"], abs(st.std - ref.std) / ref.std)
+            for mode, name in ((cs.CUBE_ACCUM_NAIVE32, "naive32"),
+                               (cs.CUBE_ACCUM_KAHAN32, "kahan32")):
+                cs.cube_set_accum_mode(mode)
+                s2 = cs.stats(t)
+                assert s2.n_valid == ref.n_valid and same_f32(s2.max, ref.max)
+                worst[name] = max(worst[name], abs(s2.std - ref.std) / ref.std)
+            cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    finally:
+        cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    print("batch64 worst std rel err:", worst)
+    assert worst["batched"] <= 1e-6
