@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         Hist H;
         const bool hist_on = hist && range.ok == 1;
         hist_setup(H, range, it.nbins, a.copies_log2, lds, acc);
-        Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f};
+        Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         Wave W = {0.f, 0, 0ull, 0ull, 0ull};
         if (hist) lds_zero(lds, it.nbins, a.copies_log2);
         if (!skip) {

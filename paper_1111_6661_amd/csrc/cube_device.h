@@ -8,8 +8,9 @@
 //   * min / max of the quieted value (v_min3/v_max3 order -0 before +0 and
 //     skip quiet NaNs; a signalling NaN is quieted first);
 //   * moments d = x - K and d^2 about a per-wavefront pivot K (the first
-//     valid voxel the wavefront meets), summed in FP32 over a short chunk and
-//     folded into a TwoSum-compensated lane accumulator (Knuth's TwoSum);
+//     valid voxel the wavefront meets), summed in FP32 over a chunk of at most
+//     two tiles and folded into a TwoSum-compensated lane accumulator
+//     (Knuth's TwoSum);
 //   * the histogram bin min(nbins-1, floor((x - lo) * scale)) in FP32 (two
 //     rounded operations, then v_cvt_flr_i32_f32), counted in LDS
 //     sub-histograms interleaved per lane; blank and out-of-range voxels go
@@ -58,7 +59,22 @@ __device__ __forceinline__ void df_add(float &ah, float &al, float bh, float bl)
 
 struct Lane {
     float mn, mx, s1, c1, s2, c2;
+    float p1, p2;  // FP32 chunk sums not yet folded into (s1, c1), (s2, c2)
 };
+
+// Fold the pending FP32 chunk sums into the compensated lane accumulators
+// (TwoSum).  Called after every second tile and at the end of every unit, so
+// a chunk spans at most two tiles (32 voxels per lane) plus head and tail.
+template <bool STATS, int ACC>
+__device__ __forceinline__ void fold(Lane &L)
+{
+    if (STATS && ACC != CUBE_ACCUM_NAIVE32) {
+        two_sum_acc(L.s1, L.c1, L.p1);
+        two_sum_acc(L.s2, L.c2, L.p2);
+        L.p1 = 0.f;
+        L.p2 = 0.f;
+    }
+}
 
 struct Wave {  // wavefront-uniform
     float K;
@@ -120,7 +136,7 @@ __device__ __forceinline__ void process(const float (&x)[NV], Lane &L, Wave &W,
     }
     // Ballot counts of this step in 32-bit scalars (at most 64 * NV each).
     unsigned int cvalid = 0, cge = 0, cle = 0;
-    float t1 = 0.f, t2 = 0.f;
+    float t1 = L.p1, t2 = L.p2;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         const float v = x[j];
@@ -168,8 +184,8 @@ __device__ __forceinline__ void process(const float (&x)[NV], Lane &L, Wave &W,
     W.ge += cge;
     W.le += cle;
     if (STATS && ACC != CUBE_ACCUM_NAIVE32) {
-        two_sum_acc(L.s1, L.c1, t1);
-        two_sum_acc(L.s2, L.c2, t2);
+        L.p1 = t1;
+        L.p2 = t2;
     }
 }
 
@@ -395,6 +411,7 @@ __device__ __forceinline__ void scan_units(const Geom &g, long long u0, long lon
                 if (++k == ntiles) break;
                 if (k + 1 < ntiles) load_tile<U>(va, q4, (k + 1) * T, B, tid);
                 process_tile<STATS, HIST, ACC, U>(vb, L, W, H);
+                fold<STATS, ACC>(L);
                 if (++k == ntiles) break;
             }
         }
@@ -409,6 +426,7 @@ __device__ __forceinline__ void scan_units(const Geom &g, long long u0, long lon
             xv[3] = have ? v.w : qnan();
             process<STATS, HIST, ACC, 4>(xv, L, W, H);
         }
+        fold<STATS, ACC>(L);
         if (++s == g.segs) {
             s = 0;
             if (++y == g.ny) {

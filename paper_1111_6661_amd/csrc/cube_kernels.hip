@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(1024) k_pass(PassArgs a)
     hist_setup(H, hr, a.nbins, a.copies_log2, lds, a.hist_acc);
     if (HIST == HIST_LDS) lds_zero(lds, a.nbins, a.copies_log2);
 
-    Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f};
+    Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     Wave W = {0.f, ACC == CUBE_ACCUM_NAIVE32 ? 1 : 0, 0ull, 0ull, 0ull};
 
     const Geom &g = a.g;
