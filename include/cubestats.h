@@ -342,7 +342,12 @@ typedef struct cube_server cube_server_t;
 
 /* slots: 1..16 concurrent batches; max_batch: queries per batch (1..4096);
  * max_inflight_bytes: device scratch budget (>= 4096); tile_voxels: 0 =
- * 2^20, else 4096..2^30.  The calling thread's current device is used. */
+ * 2^20, else 4096..2^30.  The calling thread's current device is used.
+ * Failure handling can be tested with the environment variable
+ * CUBE_FAULT_INJECT="launch:N[,M...]" (read at creation): the server's
+ * launches number N, M, ... (counted from 1) fail on the host before any
+ * work is queued; the queries of that batch complete with CUBE_EDEVICE and
+ * the server goes on serving. */
 CUBE_API int cube_server_create(int32_t mode, int32_t slots, int32_t max_batch,
                                 int64_t max_inflight_bytes, int64_t tile_voxels,
                                 cube_server_t **out);

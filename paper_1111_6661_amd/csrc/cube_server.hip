@@ -16,6 +16,7 @@
 // query at a time, in arrival order, each through the single-box entry
 // point on one stream.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -88,14 +89,41 @@ struct cube_server {
     std::vector<double> latencies;  // seconds, completed queries
     uint64_t n_done = 0, n_failed = 0;
     int64_t tile_voxels = 1 << 20;
+    uint64_t launches = 0;               // batches (or plain queries) launched
+    std::vector<uint64_t> inject_fail;   // launch numbers that fail on purpose
 };
 
 namespace {
 
 // Launch one batch (or one plain query) on a slot.  Called with the lock
 // held.  Returns CUBE_OK or the first error (then no work was queued).
+// CUBE_FAULT_INJECT="launch:N[,M...]": launches number N, M, ... (counted
+// from 1 per server) fail on the host before anything is queued, as a failed
+// launch would.  For tests of failure handling; no kernel is affected.
+std::vector<uint64_t> parse_fault_inject()
+{
+    std::vector<uint64_t> out;
+    const char *env = getenv("CUBE_FAULT_INJECT");
+    if (!env || strncmp(env, "launch:", 7) != 0) return out;
+    const char *p = env + 7;
+    while (*p) {
+        char *end = nullptr;
+        const unsigned long long v = strtoull(p, &end, 10);
+        if (end == p) break;
+        out.push_back((uint64_t)v);
+        p = *end == ',' ? end + 1 : end;
+        if (*end != ',') break;
+    }
+    return out;
+}
+
 int launch_on(cube_server *srv, Slot &sl, const std::vector<PolicyQuery> &batch)
 {
+    const uint64_t nth = ++srv->launches;
+    for (uint64_t f : srv->inject_fail)
+        if (f == nth)
+            return fail(CUBE_EDEVICE, "injected launch failure (launch %llu)",
+                        (unsigned long long)nth);
     std::vector<cube_query_t> qs;
     qs.reserve(batch.size());
     for (const PolicyQuery &p : batch) qs.push_back(srv->entries[p.id].q);
@@ -234,6 +262,7 @@ int cube_server_create(int32_t mode, int32_t slots, int32_t max_batch, int64_t m
     srv->lim.max_batch_voxels = (int64_t)1 << 32;
     if (tile_voxels) srv->tile_voxels = tile_voxels;
     srv->policy = new Policy(srv->lim);
+    srv->inject_fail = parse_fault_inject();
     hipGetDevice(&srv->device);
     srv->slots.resize((size_t)srv->lim.slots);
     for (Slot &sl : srv->slots) {

@@ -158,3 +158,32 @@ def test_early_completions_counted_once(cs):
     for i, t in enumerate(small):
         st = cs.Stats.from_bytes(out[i + 1].cpu().numpy().tobytes())
         assert st.n_valid == 4096 and st.max == float(t.max())
+
+
+def test_injected_launch_failure_is_isolated(cs, monkeypatch):
+    """A launch that fails (forced on the host: launches 2 and 4 of this
+    server) fails exactly the queries of that batch, with the error reported
+    to their waiters; the server goes on serving the rest correctly."""
+    monkeypatch.setenv("CUBE_FAULT_INJECT", "launch:2,4")
+    t = torch.randn(1 << 16, device="cuda")
+    ref = oracle.stats(t.cpu().numpy())
+    out = torch.zeros((6, 64), dtype=torch.uint8, device="cuda")
+    srv = cs.Server(cs.CUBE_SERVE_BATCHED, slots=1, max_batch=1)
+    monkeypatch.delenv("CUBE_FAULT_INJECT")
+    results = []
+    for i in range(6):     # one query per batch: submit, then wait
+        qid = srv.submit(cs.make_query(*cs.box_of(t), cs.CUBE_Q_STATS, 0, 0.0, 0.0,
+                                       out[i].data_ptr()))
+        try:
+            srv.wait(qid, timeout_s=60)
+            results.append("ok")
+        except cs.CubeError as e:
+            assert "injected" in str(e)
+            results.append("failed")
+    assert results == ["ok", "failed", "ok", "failed", "ok", "ok"]
+    _, _, n = srv.latency()
+    assert n == 4
+    srv.close()
+    torch.cuda.synchronize()
+    for i in (0, 2, 4, 5):
+        assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref, f"query {i}")
