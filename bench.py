@@ -139,7 +139,7 @@ def bench_batch64(cs, synth, torch, dev, steps: int):
           for i, (p, d) in enumerate(boxes)]
     # tile size: the fastest of a few (graph-replayed)
     tiles = {}
-    for tv in (1 << 16, 1 << 17, 1 << 18, 1 << 20):
+    for tv in (0, 1 << 16, 1 << 17, 1 << 18, 1 << 20):     # 0: each item's automatic size
         b = cs.Batch(tile_voxels=tv)
         b.enqueue(qs, sp)
         b.check()
@@ -255,9 +255,10 @@ def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7):
                                     cnt[i].data_ptr()))
         return qs, out, cnt
 
-    def replay(mode, specs, open_loop: bool):
+    def replay(mode, specs, open_loop: bool, tile: int = 0):
         qs, out, cnt = make(specs)
-        srv = cs.Server(mode, slots=4, max_batch=32, max_inflight_bytes=1 << 30)
+        srv = cs.Server(mode, slots=4, max_batch=32, max_inflight_bytes=1 << 30,
+                        tile_voxels=tile)
         ids = [0] * len(qs)
         t0 = time.perf_counter()
 
@@ -292,19 +293,22 @@ def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7):
     log(f"serve: plain capacity {cap['qps']:.0f} QPS; replaying {n} queries at {qps:.0f} QPS")
     plain, po, pc = replay(cs.CUBE_SERVE_PLAIN, specs, open_loop=True)
     served, so, sc = replay(cs.CUBE_SERVE_BATCHED, specs, open_loop=True)
-    same_counts = bool(torch.equal(pc, sc))
+    # the same stream served with one fixed 2^20-voxel tile for every query
+    fixed, fo, fc = replay(cs.CUBE_SERVE_BATCHED, specs, open_loop=True, tile=1 << 20)
+    same_counts = bool(torch.equal(pc, sc)) and bool(torch.equal(pc, fc))
     same_extrema = True
     for i in range(n):
-        if specs[i].kind == cs.CUBE_Q_STATS or True:
-            a = cs.Stats.from_bytes(po[i].cpu().numpy().tobytes())
-            b = cs.Stats.from_bytes(so[i].cpu().numpy().tobytes())
-            if a.n_valid != b.n_valid or not (a.min == b.min or a.min != a.min):
+        a = cs.Stats.from_bytes(po[i].cpu().numpy().tobytes())
+        for o in (so, fo):
+            b = cs.Stats.from_bytes(o[i].cpu().numpy().tobytes())
+            if a.n_valid != b.n_valid or a.n_nan != b.n_nan or \
+                    not (a.min == b.min or a.min != a.min) or not (a.max == b.max or a.max != a.max):
                 same_extrema = False
     del cubes
     torch.cuda.empty_cache()
     return {"cubes": len(recipes), "resident_gib": sum(r.n for r in recipes) * 4 / 2**30,
             "plain_capacity_qps": cap["qps"], "offered_qps": qps, "load_frac": load_frac,
-            "plain": plain, "served": served,
+            "plain": plain, "served": served, "served_fixed_tile_2e20": fixed,
             "p50_speedup": plain["p50_ms"] / served["p50_ms"],
             "p99_speedup": plain["p99_ms"] / served["p99_ms"],
             "results_equal_plain_vs_served": same_counts and same_extrema}
@@ -589,7 +593,9 @@ def main() -> int:
         result["p50_ms"] = sv["served"]["p50_ms"]
         result["p99_ms"] = sv["served"]["p99_ms"]
         log(f"serve: plain p50/p99 {sv['plain']['p50_ms']:.2f}/{sv['plain']['p99_ms']:.2f} ms, "
-            f"served {sv['served']['p50_ms']:.2f}/{sv['served']['p99_ms']:.2f} ms")
+            f"served {sv['served']['p50_ms']:.2f}/{sv['served']['p99_ms']:.2f} ms, "
+            f"fixed 2^20 tile {sv['served_fixed_tile_2e20']['p50_ms']:.2f}/"
+            f"{sv['served_fixed_tile_2e20']['p99_ms']:.2f} ms")
     if args.tune_save:
         cs.cube_tune_save(args.tune_save)
     print(json.dumps(result), flush=True)

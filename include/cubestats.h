@@ -267,9 +267,12 @@ typedef struct cube_batch cube_batch_t;
 CUBE_API int cube_batch_create(cube_batch_t **out);
 /* Waits for the batch's last launch, then frees everything. */
 CUBE_API void cube_batch_destroy(cube_batch_t *b);
-/* Tile size in voxels (4096..2^30; default 2^20) and threads per block (0 =
- * automatic) for later enqueues.  A query's results depend only on its own
- * data and the tile size, not on the other queries of the batch. */
+/* Tile size in voxels (4096..2^30; default 2^20; 0 = automatic per query)
+ * and threads per block (0 = automatic) for later enqueues.  The automatic
+ * size is the smallest power of two from 2^18 to 2^20 that cuts the query
+ * into at most 512 tiles, so it depends on the query alone.  A query's
+ * results depend only on its own data and its tile size, not on the other
+ * queries of the batch. */
 CUBE_API int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads);
 /* Validate the n queries (every check of the single-box calls, on the
  * host), build the work list, copy it to the device and launch, all on
@@ -342,7 +345,7 @@ typedef struct cube_server cube_server_t;
 
 /* slots: 1..16 concurrent batches; max_batch: queries per batch (1..4096);
  * max_inflight_bytes: device scratch budget (>= 4096); tile_voxels: 0 =
- * 2^20, else 4096..2^30.  The calling thread's current device is used.
+ * each query's automatic size (see cube_batch_set_tile), else 4096..2^30.  The calling thread's current device is used.
  * Failure handling can be tested with the environment variable
  * CUBE_FAULT_INJECT="launch:N[,M...]" (read at creation): the server's
  * launches number N, M, ... (counted from 1) fail on the host before any

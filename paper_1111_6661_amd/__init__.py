@@ -409,11 +409,14 @@ class Batch:
     relaunch or graph-launch it.  Outputs are the device pointers in the
     queries."""
 
-    def __init__(self, tile_voxels: int = 0, threads: int = 0):
+    def __init__(self, tile_voxels: int | None = None, threads: int = 0):
+        """tile_voxels: None keeps the library's default (2^20), 0 asks for
+        each query's automatic size."""
         self._h = C.c_void_p()
         _check(load().cube_batch_create(C.byref(self._h)))
-        if tile_voxels or threads:
-            _check(load().cube_batch_set_tile(self._h, tile_voxels or (1 << 20), threads))
+        if tile_voxels is not None or threads:
+            tv = (1 << 20) if tile_voxels is None else tile_voxels
+            _check(load().cube_batch_set_tile(self._h, tv, threads))
 
     def enqueue(self, queries, stream: int = 0) -> None:
         arr = (cube_query_t * len(queries))(*queries)

@@ -418,8 +418,8 @@ void cube_batch_destroy(cube_batch_t *b)
 int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads)
 {
     if (!b) return fail(CUBE_EINVAL, "batch is NULL");
-    if (tile_voxels < 4096 || tile_voxels > ((int64_t)1 << 30))
-        return fail(CUBE_EINVAL, "tile_voxels outside [4096, 2^30]");
+    if (tile_voxels != 0 && (tile_voxels < 4096 || tile_voxels > ((int64_t)1 << 30)))
+        return fail(CUBE_EINVAL, "tile_voxels outside [4096, 2^30] (or 0 for automatic)");
     if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
         return fail(CUBE_EINVAL, "threads must be 0, 256, 512 or 1024");
     std::lock_guard<std::mutex> lk(b->mu);
@@ -470,15 +470,25 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
         it.out = qq.out;
         it.counts = (unsigned long long *)qq.counts;
         collapse(box, &it.g);
+        // The query's tile size: the batch's, or (0) one from the query's own
+        // size, at most 512 tiles with 2^18 to 2^20 voxels each.  Below 2^18
+        // the per-tile completion (a release fence and a ticket) costs more
+        // than the parallelism it buys.  Either way a query's tiling depends
+        // only on itself, so its results are the same alone and in any mix.
+        long long tv = b->tile_voxels;
+        if (tv == 0) {
+            tv = (long long)1 << 18;
+            while (tv < ((long long)1 << 20) && tv * 512 < (long long)box.n) tv <<= 1;
+        }
         // Segments of at most one tile; whole rows per tile when rows are short.
         Geom &g = it.g;
-        long long seg = g.row_len < b->tile_voxels ? g.row_len : b->tile_voxels;
+        long long seg = g.row_len < tv ? g.row_len : tv;
         seg = (seg + 3) & ~3LL;
         if (seg < 4) seg = 4;
         g.seg_len = seg;
         g.segs = box.n == 0 ? 1 : (g.row_len + seg - 1) / seg;
         g.n_units = box.n == 0 ? 0 : g.ny * g.nz * g.segs;
-        long long upt = b->tile_voxels / seg;
+        long long upt = tv / seg;
         if (upt < 1) upt = 1;
         it.units_per_tile = upt;
         const long long nt = g.n_units == 0 ? 1 : (g.n_units + upt - 1) / upt;

@@ -88,7 +88,7 @@ struct cube_server {
     std::unordered_map<uint64_t, Entry> entries;
     std::vector<double> latencies;  // seconds, completed queries
     uint64_t n_done = 0, n_failed = 0;
-    int64_t tile_voxels = 1 << 20;
+    int64_t tile_voxels = 0;             // 0: each query's own automatic size
     uint64_t launches = 0;               // batches (or plain queries) launched
     std::vector<uint64_t> inject_fail;   // launch numbers that fail on purpose
 };

@@ -68,7 +68,7 @@ def check_query(cs, outs, i, t, kind, nb):
                             f"item {i} minmax")
 
 
-@pytest.mark.parametrize("tile", [4096, 1 << 16, 1 << 20])
+@pytest.mark.parametrize("tile", [4096, 1 << 16, 1 << 20, 0])
 def test_mixed_batch_matches_oracle(cs, tile):
     items = make_items()
     kinds = [cs.CUBE_Q_STATS, cs.CUBE_Q_HIST, cs.CUBE_Q_FUSED, cs.CUBE_Q_MINMAX]
@@ -110,6 +110,38 @@ def test_alone_equals_in_mix(cs):
         assert torch.equal(alone.cnt[0], mix.cnt[i]), f"item {i} counts differ alone vs mix"
         b2.close()
     b.close()
+
+
+def test_automatic_tile_sizes(cs):
+    """Tile 0: each query takes the smallest power of two from 2^18 to 2^20
+    voxels that cuts it into at most 512 tiles.  Items here take 2^18, 2^19
+    and 2^20; each gives the same bits alone and in the mix, and agrees with
+    the oracle."""
+    import synth
+    shapes = [(37, 11, 5), (200, 300, 9),            # one tile of 2^18
+              (1000, 1000, 100),                     # 10^8 voxels: 2^18
+              (2048, 1024, 96),                      # 2^27.6 voxels: 2^19
+              (2048, 1024, 160)]                     # 2^28.3 voxels: 2^20 (clamped)
+    items = [synth.cube_tensor(synth.WORKLOADS["tiny"].scaled(nx, ny, nz), 4200 + k, device="cuda")
+             for k, (nx, ny, nz) in enumerate(shapes)]
+    kinds = [cs.CUBE_Q_FUSED, cs.CUBE_Q_MINMAX]
+    nbins_list = [1024, 333]
+    mix = Outputs(len(items), 1024)
+    b = cs.Batch(tile_voxels=0)
+    b.enqueue(queries_for(cs, items, mix, kinds, nbins_list))
+    b.check()
+    for i, t in enumerate(items):
+        alone = Outputs(1, 1024)
+        b2 = cs.Batch(tile_voxels=0)
+        b2.enqueue(queries_for(cs, [t], alone, [kinds[i % 2]], [nbins_list[i % 2]]))
+        b2.check()
+        b2.close()
+        assert torch.equal(alone.out[0], mix.out[i]), f"item {i} stats differ alone vs mix"
+        assert torch.equal(alone.cnt[0], mix.cnt[i]), f"item {i} counts differ alone vs mix"
+        check_query(cs, mix, i, t, kinds[i % 2], nbins_list[i % 2])
+    b.close()
+    del items
+    torch.cuda.empty_cache()
 
 
 def test_batch_of_workload_items(cs):

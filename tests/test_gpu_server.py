@@ -55,9 +55,11 @@ def random_queries(cs, cubes, n, seed, nbins_max=1024):
     return specs, out, cnt
 
 
-def test_server_mix_equals_alone(cs, cubes):
+@pytest.mark.parametrize("tile", [1 << 16, 0])
+def test_server_mix_equals_alone(cs, cubes, tile):
+    """tile 0: each query's automatic tile size (the server's default)."""
     specs, out, cnt = random_queries(cs, cubes, 60, seed=3)
-    srv = cs.Server(cs.CUBE_SERVE_BATCHED, slots=3, max_batch=8, tile_voxels=1 << 16)
+    srv = cs.Server(cs.CUBE_SERVE_BATCHED, slots=3, max_batch=8, tile_voxels=tile)
     # submit from two threads with staggered arrivals
     ids = [None] * len(specs)
 
@@ -82,7 +84,7 @@ def test_server_mix_equals_alone(cs, cubes):
         o1 = torch.zeros(64, dtype=torch.uint8, device="cuda")
         c1 = torch.zeros(nb + 3, dtype=torch.int64, device="cuda")
         q1 = cs.make_query(q.ptr, list(q.dims), kind, nb, lo, hi, o1.data_ptr(), c1.data_ptr())
-        b = cs.Batch(tile_voxels=1 << 16)
+        b = cs.Batch(tile_voxels=tile)
         b.enqueue([q1])
         b.check()
         b.close()
