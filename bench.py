@@ -487,6 +487,12 @@ def main() -> int:
     def two_pass():
         cs.cube_stats_hist_minmax_async(ptr, dims, nbins, out.data_ptr(), counts.data_ptr(), sp)
 
+    probe_word = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def read_probe():
+        # the fused pass's reads alone (same launch shape and order)
+        cs.cube_read_probe(ptr, dims, nbins, probe_word.data_ptr(), sp)
+
     # A plain copy of known size (1 GiB read + 1 GiB written), outside the
     # timed region: profiler byte counters are scaled by what they read for it.
     cal_src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -512,6 +518,13 @@ def main() -> int:
 
     extra = {}
     n_short = max(5, args.steps // 2)
+    _, probe_ms = time_launches(read_probe, stream, n_short, 2)
+    probe_gbs = 4 * r.n / (probe_ms * 1e-3) / 1e9
+    extra["read_probe"] = {"ms_per_call_events": round(probe_ms, 4), "gbs": probe_gbs,
+                           "frac_hbm_peak": probe_gbs / HBM_PEAK_GBS,
+                           "fused_frac_of_probe": probe_ms / ev_ms}
+    log(f"read probe: {probe_ms:.4f} ms ({probe_gbs:.0f} GB/s); fused reaches "
+        f"{100 * probe_ms / ev_ms:.1f} % of it")
     others = () if args.only_fused else (("stats_only", stats_only), ("hist_only", hist_only),
                                           ("two_pass_minmax", two_pass))
     for label, fn in others:
@@ -567,6 +580,8 @@ def main() -> int:
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic(),
                      "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "read_probe_gbs": probe_gbs,
+                     "frac_of_read_probe": achieved / probe_gbs,
                      "kernel_sources": kernel_source_hash()},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "kernel_ms_events": ev_ms,

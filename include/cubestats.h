@@ -217,6 +217,22 @@ CUBE_API int cube_project(const float *ptr, const int64_t *dims, float *mip, dou
                           uint32_t *nvalid, void *stream);
 
 /*
+ * Read probe: the read ceiling of the fused pass's access pattern, the
+ * figure the fused pass's HBM rate is measured against.  Reads every voxel of
+ * the DEVICE box once, in the launch shape the fused statistics-and-histogram
+ * pass would use for `nbins` bins (grid, block size, dynamic LDS, tiles per
+ * lane, work units per block), doing one bitwise OR per voxel.  ORs the bit
+ * patterns of all voxels (NaNs included) into *dev_out, a 4-byte-aligned
+ * DEVICE word that the caller zeroes beforehand; the box's own OR is
+ * therefore known exactly.  Stream-ordered on `stream` (NULL = the default
+ * stream); an empty box launches nothing.  Errors: CUBE_EINVAL for the box
+ * errors of the other calls, nbins outside [1, CUBE_MAX_BINS] or a NULL or
+ * misaligned dev_out; CUBE_EDEVICE for a HIP error.
+ */
+CUBE_API int cube_read_probe(const float *ptr, const int64_t *dims, int32_t nbins,
+                             uint32_t *dev_out, void *stream);
+
+/*
  * Autotuner.  Times candidate launch shapes (threads, float4 loads per tile,
  * LDS histogram copies, blocks per CU) of one pass kind -- CUBE_Q_STATS,
  * CUBE_Q_HIST or CUBE_Q_FUSED over [lo, hi] -- on the given DEVICE box

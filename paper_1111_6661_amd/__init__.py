@@ -121,6 +121,8 @@ def load() -> C.CDLL:
                                         C.POINTER(C.c_uint64), i32]
     lib.cube_project.argtypes = [P, I64P, P, P, P, P]
     lib.cube_project.restype = C.c_int
+    lib.cube_read_probe.argtypes = [P, I64P, i32, P, P]
+    lib.cube_read_probe.restype = C.c_int
     lib.cube_host_query.argtypes = [C.POINTER(cube_query_t), i64]
     lib.cube_host_query.restype = C.c_int
     lib.cube_select.argtypes = [P, I64P, C.c_uint64, C.POINTER(C.c_float)]
@@ -358,6 +360,23 @@ def project(t):
     cube_project(ptr, d, mip.data_ptr(), mom0.data_ptr(), nv.data_ptr(),
                  torch.cuda.current_stream(t.device).cuda_stream)
     return mip, mom0, nv
+
+
+def cube_read_probe(ptr: int, dims, nbins: int, dev_out: int, stream: int = 0) -> None:
+    """OR the bit patterns of the box into the device word at dev_out, read
+    in the fused pass's launch shape for nbins bins."""
+    _check(load().cube_read_probe(C.c_void_p(ptr), _dims(dims), nbins, C.c_void_p(dev_out),
+                                  C.c_void_p(stream or None)))
+
+
+def read_probe(t, nbins: int = 1024) -> int:
+    """The OR of the bit patterns of a CUDA tensor's voxels, read by the probe
+    kernel on the current stream (synchronous)."""
+    import torch
+    ptr, d = box_of(t)
+    out = torch.zeros(1, dtype=torch.int32, device=t.device)
+    cube_read_probe(ptr, d, nbins, out.data_ptr(), torch.cuda.current_stream(t.device).cuda_stream)
+    return int(out.cpu().numpy().view(np.uint32)[0])
 
 
 def host_box_of(a) -> tuple:

@@ -95,6 +95,11 @@ int cu_count();
 int accum_mode();
 void get_launch(int *threads, int *blocks, int *copies, int *unroll);
 
+// The launch shape of one pass over a validated box: statistics (`stats`)
+// and/or a histogram (hist_kind_req 1) of nbins bins; the explicit shape of
+// cube_set_launch, else the tuned one, else the default rules.
+int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p);
+
 // One pass over a validated device box on stream `s`, with the calling
 // stream's workspace: statistics (to dev_out) and/or a histogram (HIST_NONE
 // or HIST_LDS requested) over `range`, or over `dev_range` when it is not

@@ -56,6 +56,7 @@ def test_brick16g_full_cube(cs):
     k_mid = (int(st_fused_ref.n_valid) - 1) // 2
     sel = {k: cs.select(t, k) for k in (0, k_mid, int(st_fused_ref.n_valid) - 1)}
     med, med_nv = cs.median(t)
+    probe = cs.read_probe(t, nb)
     t0 = time.perf_counter()
     host = _host_copy(t)
     del t
@@ -69,6 +70,8 @@ def test_brick16g_full_cube(cs):
     assert_counts_match(counts, want, "fused counts")
     assert_counts_match(counts2, want, "two-pass counts")
     assert int(want.sum()) == r.n
+    # the read probe saw every voxel's bits
+    assert probe == int(np.bitwise_or.reduce(host.view(np.uint32).reshape(-1)))
     # Selection at full size, by the rank property that fixes the k-th
     # smallest: at most k valid voxels lie below it and more than k at or
     # below it (so it is one of the voxels).  The extremes are the min/max.
