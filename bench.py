@@ -59,8 +59,9 @@ def time_launches(fn, stream, steps: int, warmup: int):
         b.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    ev = sum(a.elapsed_time(b) for a, b in evs) / steps
-    return wall, ev
+    per = [a.elapsed_time(b) for a, b in evs]
+    time_launches.last = per          # per-launch event times of the last call
+    return wall, sum(per) / steps
 
 
 KERNEL_SOURCES = ("paper_1111_6661_amd/csrc/cube_device.h",
@@ -98,26 +99,46 @@ def profiled_traffic():
     return None
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cube, nbins: int, lo: float, hi: float, target_s: float):
-    """The oracle on the first planes of the cube, sized to about target_s."""
+    """The oracle on the first planes of the cube, sized to about target_s,
+    on one host core (the calling thread pinned to it while it runs)."""
     import oracle
     nz, ny, nx = cube.shape
     plane = nx * ny
     probe = cube[:1].cpu().numpy()
-    t0 = time.perf_counter()
-    oracle.stats(probe)
-    oracle.hist(probe, lo, hi, nbins)
-    per_plane = max(time.perf_counter() - t0, 1e-6)
-    k = int(max(1, min(nz, target_s / per_plane)))
-    sample = cube[:k].cpu().numpy()
-    t0 = time.perf_counter()
-    oracle.stats(sample)
-    oracle.hist(sample, lo, hi, nbins)
-    dt = time.perf_counter() - t0
+    old = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    core = min(old) if old else None
+    try:
+        if core is not None:
+            os.sched_setaffinity(0, {core})
+        t0 = time.perf_counter()
+        oracle.stats(probe)
+        oracle.hist(probe, lo, hi, nbins)
+        per_plane = max(time.perf_counter() - t0, 1e-6)
+        k = int(max(1, min(nz, target_s / per_plane)))
+        sample = cube[:k].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.stats(sample)
+        oracle.hist(sample, lo, hi, nbins)
+        dt = time.perf_counter() - t0
+    finally:
+        if core is not None:
+            os.sched_setaffinity(0, old)
     return {"value": k * plane / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
             "sample": f"first {k} of {nz} channel planes ({k * plane} voxels): oracle stats "
                       f"(two sweeps) + histogram (one sweep), {dt:.1f} s single-threaded",
-            "seconds": dt}
+            "seconds": dt, "pinned_core": core, "cpu_model": _cpu_model(),
+            "host_cores": os.cpu_count()}
 
 
 def bench_batch64(cs, synth, torch, dev, steps: int):
@@ -227,10 +248,13 @@ def bench_stress(cs, synth, torch, dev, steps: int, tune: bool = False):
                                           for k, v in modes.items()}}
 
 
-def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7):
+def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7,
+                sweep=()):
     """Twelve resident cubes (about 201 GiB); a seeded Poisson query stream at
     load_frac of the plain server's closed-loop capacity, replayed against the
-    plain server and the continuous-batching server."""
+    plain server and the continuous-batching server (and the latter with a
+    fixed 2^20-voxel tile).  Each load in `sweep` replays a stream of its own
+    against plain and served."""
     import threading
     from paper_1111_6661_amd import workloads
     recipes = synth.serve_recipes()
@@ -304,13 +328,26 @@ def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7):
             if a.n_valid != b.n_valid or a.n_nan != b.n_nan or \
                     not (a.min == b.min or a.min != a.min) or not (a.max == b.max or a.max != a.max):
                 same_extrema = False
+    loads = {}
+    for k, lf in enumerate(sweep):
+        q2 = lf * cap["qps"]
+        n2 = max(50, int(q2 * seconds))
+        sp2 = workloads.query_stream(shapes, ranges, n2, q2, synth.BASE_SEED + 32 + k,
+                                     cs.CUBE_Q_STATS, cs.CUBE_Q_FUSED)
+        p2, _, pc2 = replay(cs.CUBE_SERVE_PLAIN, sp2, open_loop=True)
+        s2, _, sc2 = replay(cs.CUBE_SERVE_BATCHED, sp2, open_loop=True)
+        same_counts = same_counts and bool(torch.equal(pc2, sc2))
+        loads[str(lf)] = {"offered_qps": q2, "queries": n2, "plain": p2, "served": s2}
+        log(f"serve at {lf}x: plain p50/p99 {p2['p50_ms']:.2f}/{p2['p99_ms']:.2f} ms, "
+            f"served {s2['p50_ms']:.2f}/{s2['p99_ms']:.2f} ms")
     del cubes
     torch.cuda.empty_cache()
     return {"cubes": len(recipes), "resident_gib": sum(r.n for r in recipes) * 4 / 2**30,
             "plain_capacity_qps": cap["qps"], "offered_qps": qps, "load_frac": load_frac,
-            "plain": plain, "served": served, "served_fixed_tile_2e20": fixed,
+            "queries": n, "plain": plain, "served": served, "served_fixed_tile_2e20": fixed,
             "p50_speedup": plain["p50_ms"] / served["p50_ms"],
             "p99_speedup": plain["p99_ms"] / served["p99_ms"],
+            "load_sweep": loads,
             "results_equal_plain_vs_served": same_counts and same_extrema}
 
 
@@ -427,6 +464,8 @@ def main() -> int:
     ap.add_argument("--no-select", action="store_true", help="skip selection and median")
     ap.add_argument("--no-host", action="store_true", help="skip the out-of-core host queries")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-sweep", default="",
+                    help="more offered loads (fractions of the plain capacity), e.g. 0.5,0.9")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -506,6 +545,7 @@ def main() -> int:
     torch.cuda.synchronize()
     wall_ms, ev_ms = time_launches(fused, stream, args.steps, args.warmup)
     torch.cuda.synchronize()
+    ev_median_ms = float(np.median(time_launches.last))
     st = cs.Stats.from_bytes(out.cpu().numpy().tobytes())
     c = counts.cpu().numpy().view(np.uint64)
     log(f"fused: {ev_ms:.4f} ms/launch (events), {wall_ms:.4f} ms/step wall")
@@ -585,6 +625,7 @@ def main() -> int:
                      "kernel_sources": kernel_source_hash()},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "kernel_ms_events": ev_ms,
+        "kernel_ms_events_median": ev_median_ms,
         "parity": parity,
         "extra": extra,
     }
@@ -603,7 +644,8 @@ def main() -> int:
     if not args.only_fused and not args.no_serve:
         cube = None
         torch.cuda.empty_cache()
-        sv = bench_serve(cs, synth, torch, dev, args.serve_seconds)
+        sweep = [float(v) for v in args.serve_sweep.split(",") if v.strip()]
+        sv = bench_serve(cs, synth, torch, dev, args.serve_seconds, sweep=sweep)
         extra["serve"] = sv
         result["p50_ms"] = sv["served"]["p50_ms"]
         result["p99_ms"] = sv["served"]["p99_ms"]
