@@ -105,6 +105,9 @@ class Oracle:
         lib.oracle_median.argtypes = [P, i64, i64, i64, i64, i64, C.POINTER(f64),
                                       C.POINTER(C.c_uint64)]
         lib.oracle_median.restype = C.c_int
+        lib.oracle_quantiles.argtypes = [P, i64, i64, i64, i64, i64, P, C.c_int32, P,
+                                         C.POINTER(C.c_uint64)]
+        lib.oracle_quantiles.restype = C.c_int
         lib.oracle_project.argtypes = [P, i64, i64, i64, i64, i64, P, P, P]
         lib.oracle_project.restype = C.c_int
         self.lib = lib
@@ -153,6 +156,18 @@ class Oracle:
         if self.lib.oracle_median(*box_of(a), C.byref(m), C.byref(n)) != 0:
             raise ValueError("no valid voxel or invalid box")
         return m.value
+
+    def quantiles(self, a: np.ndarray, q) -> np.ndarray:
+        """Quantiles (linear interpolation between the valid voxels around
+        rank q * (n_valid - 1)) at the levels q, as float64."""
+        qa = np.ascontiguousarray(np.atleast_1d(np.asarray(q, dtype=np.float64)))
+        out = np.empty(qa.size, dtype=np.float64)
+        n = C.c_uint64()
+        rc = self.lib.oracle_quantiles(*box_of(a), qa.ctypes.data, qa.size, out.ctypes.data,
+                                       C.byref(n))
+        if rc != 0:
+            raise ValueError("invalid box, level outside [0, 1], or no valid voxel")
+        return out
 
     def project(self, a: np.ndarray):
         """(mip float32 [ny, nx], mom0 float64 [ny, nx], nvalid uint32 [ny, nx])
@@ -235,6 +250,10 @@ def select(a, k):
 
 def median(a):
     return default().median(a)
+
+
+def quantiles(a, q):
+    return default().quantiles(a, q)
 
 
 def project(a):

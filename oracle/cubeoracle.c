@@ -27,6 +27,12 @@
  *                  with -0 before +0; median = select((n-1)/2) for odd
  *                  n_valid, the FP64 mean of select(n/2-1) and select(n/2)
  *                  for even n_valid (the median task of Section 3).
+ *   quantile(q)  : for 0 <= q <= 1, with n = n_valid, h = q * (n - 1) in FP64,
+ *                  j = floor(h), f = h - j, a = select(j) and b = select(j+1)
+ *                  (b = a when f == 0): the linear interpolation a + f*(b - a)
+ *                  in FP64 (Hyndman and Fan's definition 7, numpy's default).
+ *                  When a == b the result is a; an infinite end point is the
+ *                  result (a = -Inf or b = +Inf), and -Inf to +Inf gives NaN.
  *
  *   projections along the channel axis, per spatial pixel (x, y) over the
  *   channels z of the box (the maps shown beside a rendered cube):
@@ -339,6 +345,59 @@ int oracle_median(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t sy
         if (oracle_select(p, nx, ny, nz, sy, sz, st.n_valid / 2, &b)) return -1;
         *median = ((double)a + (double)b) / 2.0;
     }
+    return 0;
+}
+
+/*
+ * Quantiles of the valid voxels (see the header): one sort, then for every
+ * level q[i] the interpolation between the two valid voxels around rank
+ * q[i] * (n - 1).  Returns 0, or -1 for an invalid box, a level outside
+ * [0, 1] (NaN included) or no valid voxel, or -2 when the copy cannot be
+ * allocated.  *n_valid is set whenever the box is valid.
+ */
+int oracle_quantiles(const float *p, int64_t nx, int64_t ny, int64_t nz, int64_t sy,
+                     int64_t sz, const double *q, int32_t m, double *out, uint64_t *n_valid)
+{
+    if (!dims_ok(nx, ny, nz, sy, sz) || m < 1) return -1;
+    uint64_t n = 0, cap = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
+    float *v = (float *)malloc((cap ? cap : 1) * sizeof(float));
+    if (!v) return -2;
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                float w = p[x + sy * y + sz * z];
+                if (w != w) continue;  /* blank */
+                v[n++] = w;
+            }
+    *n_valid = n;
+    int rc = 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (!(q[i] >= 0.0 && q[i] <= 1.0)) rc = -1;
+    if (n == 0 || rc) {
+        free(v);
+        return -1;
+    }
+    qsort(v, (size_t)n, sizeof(float), cmp_float);
+    for (int32_t i = 0; i < m; ++i) {
+        double h = q[i] * (double)(n - 1);
+        double j = floor(h);
+        double f = h - j;
+        double a = v[(uint64_t)j];
+        double b = f > 0.0 ? v[(uint64_t)j + 1] : a;
+        double r;
+        if (a == b)
+            r = a;
+        else if (isinf(a) && isinf(b))
+            r = NAN;
+        else if (isinf(a))
+            r = a;
+        else if (isinf(b))
+            r = b;
+        else
+            r = a + f * (b - a);
+        out[i] = r;
+    }
+    free(v);
     return 0;
 }
 

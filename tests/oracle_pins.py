@@ -358,6 +358,61 @@ def pin_select(o):
         raise AssertionError("accepted an out-of-range rank")
 
 
+def pin_quantiles(o):
+    """Quantiles against closed forms (a shuffled integer ramp, where every
+    interpolated level is exact), numpy's own quantile (linear method, to a
+    few ulps, as it rounds its interpolation differently), the extremes and
+    median from other oracle routines, and the readings for infinities."""
+    rng = np.random.default_rng(31)
+    # ramp 0..N-1 shuffled, with NaNs put between: quantile(q) = q * (N - 1)
+    N = 1001
+    ramp = rng.permutation(np.arange(N, dtype=np.float32))
+    a = np.full(N + 40, np.nan, dtype=np.float32)
+    keep = np.sort(rng.choice(N + 40, N, replace=False))
+    a[keep] = ramp
+    qs = [0.0, 0.001, 0.25, 0.5, 0.3337, 0.75, 0.999, 1.0]
+    got = o.quantiles(a, qs)
+    for q, g in zip(qs, got):
+        assert g == q * (N - 1), (q, g)
+    # a ramp of step 2 with offset: a + 2h
+    b = (np.arange(200, dtype=np.float32) * 2 + 7)[::-1].copy()
+    assert list(o.quantiles(b, [0.5, 0.25, 0.0625])) == [7 + 2 * 99.5, 7 + 2 * 49.75, 7 + 2 * 12.4375]
+    # random values: numpy's linear quantile, the extremes and the median
+    for n in (1, 2, 5, 1000):
+        v = (rng.standard_normal(n) * 30).astype(np.float32)
+        v[rng.random(n) < 0.1] = np.nan
+        valid = v[~np.isnan(v)].astype(np.float64)
+        if valid.size == 0:
+            continue
+        lv = [0.0, 0.1, 0.5, 0.9, 1.0]
+        got = o.quantiles(v, lv)
+        want = np.quantile(valid, lv)
+        assert np.allclose(got, want, rtol=1e-14, atol=1e-12), (n, got, want)
+        st = o.stats(v)
+        assert got[0] == st.min and got[-1] == st.max
+        assert got[2] == o.median(v)
+        assert all(got[i] <= got[i + 1] for i in range(len(got) - 1))
+    # infinities: an infinite end point is the result; -Inf to +Inf is NaN
+    w = np.array([-np.inf, 1.0, 2.0, np.nan, np.inf], dtype=np.float32)
+    r = o.quantiles(w, [0.0, 1 / 6, 0.5, 5 / 6, 1.0])
+    assert r[0] == -np.inf and r[1] == -np.inf and r[2] == 1.5 and r[3] == np.inf
+    assert r[4] == np.inf
+    assert np.isnan(o.quantiles(np.array([-np.inf, np.inf], np.float32), [0.5])[0])
+    # repeated values: no interpolation between equal neighbours
+    assert list(o.quantiles(np.array([9, 3, 3, 9, 3], np.float32), [0.25, 0.375, 0.625])) == \
+        [3.0, 3.0, 6.0]
+    # signed zeros order -0 before +0
+    z = o.quantiles(np.array([0.0, -0.0, -0.0], np.float32), [0.0, 1.0])
+    assert signbit(z[0]) and not signbit(z[1])
+    # errors: a level outside [0, 1] or NaN, and no valid voxel
+    for bad_q, arr in (([1.5], a), ([-0.1], a), ([np.nan], a), ([0.5], np.full(4, np.nan, np.float32))):
+        try:
+            o.quantiles(arr, bad_q)
+        except ValueError:
+            continue
+        raise AssertionError(f"accepted {bad_q}")
+
+
 def pin_project(o):
     """Projections along z against numpy reductions over axis 0, exact sums
     (math.fsum) and the -0 < +0 order, plus consistency with the global
@@ -413,4 +468,5 @@ def pin_project(o):
 ALL_PINS = [pin_textbook, pin_exact_rational, pin_closed_forms, pin_merge,
             pin_extrema_nan, pin_strided, pin_hist_ramp, pin_hist_unit_scale,
             pin_hist_edges, pin_hist_subnormal, pin_hist_rounding_model, pin_hist_numpy,
-            pin_hist_invariants, pin_hist_validation, pin_select, pin_project]
+            pin_hist_invariants, pin_hist_validation, pin_select, pin_quantiles,
+            pin_project]

@@ -45,6 +45,11 @@ MUTANTS = {
     "select_includes_nan": ("if (f == f) v[n++] = f;", "v[n++] = f;"),
     "select_reversed": ("if (before(x, y)) return -1;", "if (before(x, y)) return 1;"),
     "median_upper_only": ("*median = ((double)a + (double)b) / 2.0;", "*median = (double)b;"),
+    "quantile_includes_nan": ("if (w != w) continue;  /* blank */", ""),
+    "quantile_upper_rank": ("double a = v[(uint64_t)j];", "double a = v[(uint64_t)ceil(h)];"),
+    "quantile_fraction_flipped": ("r = a + f * (b - a);", "r = b - f * (b - a);"),
+    "quantile_rank_of_n": ("double h = q[i] * (double)(n - 1);", "double h = q[i] * (double)n;"),
+    "quantile_inf_not_kept": ("        else if (isinf(a))\n            r = a;\n", ""),
     "project_wrong_axis": ("float f = p[x + sy * y + sz * z];\n                if (f != f) continue;",
                            "float f = p[x + sy * z + sz * y];\n                if (f != f) continue;"),
     "project_min_not_max": ("if (n == 0 || before(mx, f)) mx = f;",

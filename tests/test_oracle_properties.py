@@ -92,6 +92,13 @@ def test_selection_and_projection_agree_with_stats(a):
                         abs_tol=1e-9 * s.mean_abs * s.n_valid)
     m = oracle.median(a)
     assert s.min <= m <= s.max
+    # quantiles: the extremes at 0 and 1, the median at 1/2 (to rounding:
+    # the median averages, the quantile interpolates), monotone in the level
+    levels = [0.0, 0.1, 0.5, 0.9, 1.0]
+    qv = oracle.quantiles(a, levels)
+    assert qv[0] == s.min and qv[-1] == s.max
+    assert math.isclose(qv[2], m, rel_tol=1e-15, abs_tol=1e-300)
+    assert all(qv[i] <= qv[i + 1] for i in range(len(qv) - 1))
     # the median splits the valid voxels: at most half lie strictly below it
     # and at most half strictly above it
     v = a[~np.isnan(a)]
