@@ -372,6 +372,15 @@ def bench_select(cs, torch, cube, n_valid: int, reps: int):
     for _ in range(reps):
         m, nv = cs.median(cube)
     med_ms = (time.perf_counter() - t0) * 1e3 / reps
+    # quantiles: the quartiles, and 64 levels at once (three reads each)
+    qtimes = {}
+    for label, lv in (("quartiles", [0.25, 0.5, 0.75]),
+                      ("levels64", [i / 63 for i in range(64)])):
+        cs.quantiles(cube, lv)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            qv, _ = cs.quantiles(cube, lv)
+        qtimes[label] = round((time.perf_counter() - t0) * 1e3 / reps, 4)
     flat = cube.view(-1)
     below = int((flat < v).sum())
     at_or_below = int((flat <= v).sum())
@@ -379,6 +388,9 @@ def bench_select(cs, torch, cube, n_valid: int, reps: int):
     return {"rank": k, "value": v, "median": m, "n_valid": nv,
             "select_ms": round(sel_ms, 4), "median_ms": round(med_ms, 4),
             "select_gbs_2_passes": 2 * 4 * n / (sel_ms * 1e-3) / 1e9,
+            "quantiles_ms": qtimes,
+            "quantiles_gbs_3_passes": {kq: 3 * 4 * n / (v_ * 1e-3) / 1e9
+                                       for kq, v_ in qtimes.items()},
             "rank_property_holds": below <= k < at_or_below and nv == n_valid}
 
 
@@ -583,7 +595,8 @@ def main() -> int:
         sel = bench_select(cs, torch, cube, int(st0.n_valid), 5)
         extra["select_median"] = sel
         parity["median_rank_property"] = sel["rank_property_holds"]
-        log(f"select: {sel['select_ms']:.3f} ms, median: {sel['median_ms']:.3f} ms")
+        log(f"select: {sel['select_ms']:.3f} ms, median: {sel['median_ms']:.3f} ms, "
+            f"quantiles: {sel['quantiles_ms']}")
     if not args.only_fused:
         pj = bench_project(cs, torch, cube, stream, n_short)
         extra["project"] = pj

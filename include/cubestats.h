@@ -196,6 +196,30 @@ CUBE_API int cube_median(const float *ptr, const int64_t *dims, double *median,
                          uint64_t *n_valid);
 
 /*
+ * Quantiles of the valid voxels of a DEVICE box at m levels q[0..m-1]
+ * (host array, each in [0, 1]; 1 <= m <= CUBE_MAX_QUANTILES).  With n the
+ * number of valid voxels, level q takes h = q (n - 1) in FP64, j = floor(h),
+ * f = h - j, the valid voxels a and b of ranks j and j + 1 (b = a when
+ * f == 0; ranks in the order by value with -0 before +0) and gives
+ * a + f (b - a) in FP64: the linear-interpolation quantile (Hyndman and
+ * Fan's definition 7), so q = 0 and 1 give the minimum and maximum.  When
+ * a == b the result is a; an infinite end point is the result (a = -Inf or
+ * b = +Inf) and -Inf to +Inf gives NaN.  At q = 1/2 this is the median up to
+ * rounding: cube_median averages (a + b) / 2 instead.
+ * Results go to out[0..m-1] (host), the valid count to *n_valid (host; may
+ * be NULL).  Three reads of the box for up to eight distinct leading
+ * 12-bit key buckets among the ranks wanted, one more read per further
+ * eight; synchronous on the null stream.  Keeps about 300 KB of device and
+ * pinned host memory per device until cube_shutdown.  Errors: CUBE_EINVAL
+ * for the box errors of the other calls, an empty box, no valid voxel (with
+ * *n_valid = 0), NULL q or out, m outside its range or a level outside
+ * [0, 1] (NaN included); CUBE_EDEVICE for a HIP error.
+ */
+#define CUBE_MAX_QUANTILES 64
+CUBE_API int cube_quantiles(const float *ptr, const int64_t *dims, const double *q, int32_t m,
+                            double *out, uint64_t *n_valid);
+
+/*
  * Projections along the channel axis z: the maps a viewer of spectral cubes
  * shows beside the rendered volume (Section 2).  For every spatial pixel
  * (x, y) of the box, over its nz channels:

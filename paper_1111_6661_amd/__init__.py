@@ -129,6 +129,8 @@ def load() -> C.CDLL:
     lib.cube_select.restype = C.c_int
     lib.cube_median.argtypes = [P, I64P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     lib.cube_median.restype = C.c_int
+    lib.cube_quantiles.argtypes = [P, I64P, P, i32, P, C.POINTER(C.c_uint64)]
+    lib.cube_quantiles.restype = C.c_int
     lib.cube_autotune.argtypes = [P, I64P, i32, f32, f32, i32, i32, C.c_char_p, C.c_size_t]
     lib.cube_autotune.restype = C.c_int
     lib.cube_tune_save.argtypes = [C.c_char_p]
@@ -246,6 +248,24 @@ def cube_median(ptr: int, dims):
     m, n = C.c_double(), C.c_uint64()
     _check(load().cube_median(C.c_void_p(ptr), _dims(dims), C.byref(m), C.byref(n)))
     return m.value, n.value
+
+
+CUBE_MAX_QUANTILES = 64
+
+
+def cube_quantiles(ptr: int, dims, q):
+    """(float64 array of the quantiles at levels q, n_valid) of a device box."""
+    qa = np.ascontiguousarray(np.atleast_1d(np.asarray(q, dtype=np.float64)))
+    out = np.empty(qa.size, dtype=np.float64)
+    n = C.c_uint64()
+    _check(load().cube_quantiles(C.c_void_p(ptr), _dims(dims), C.c_void_p(qa.ctypes.data),
+                                 qa.size, C.c_void_p(out.ctypes.data), C.byref(n)))
+    return out, n.value
+
+
+def quantiles(t, q):
+    ptr, d = box_of(t)
+    return cube_quantiles(ptr, d, q)
 
 
 def select(t, rank: int) -> float:

@@ -629,6 +629,7 @@ void cube_shutdown(void)
 {
     host_release();
     project_release();
+    quant_release();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &kv : g_ws) free_ws(kv.second);
     g_ws.clear();

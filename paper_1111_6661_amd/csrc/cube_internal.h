@@ -115,6 +115,8 @@ int write_empty(cube_stats_t *dev_out, unsigned long long *dev_counts, int nbins
 void host_release();
 // Release the projection slice partials (cube_project.hip).
 void project_release();
+// Release the quantile counters and tables (cube_quantile.hip).
+void quant_release();
 
 // A launch shape chosen by the autotuner (cube_tune.hip).
 struct TunedShape {

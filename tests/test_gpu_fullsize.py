@@ -57,6 +57,15 @@ def test_brick16g_full_cube(cs):
     sel = {k: cs.select(t, k) for k in (0, k_mid, int(st_fused_ref.n_valid) - 1)}
     med, med_nv = cs.median(t)
     probe = cs.read_probe(t, nb)
+    # quantiles at two levels whose ranks need interpolation, and the voxels
+    # of the two ranks around each
+    qlv = [0.25, 0.9]
+    qv, qn = cs.quantiles(t, qlv)
+    qpairs = []
+    for lvl in qlv:
+        h = lvl * (qn - 1)
+        j = int(np.floor(h))
+        qpairs.append((j, h - j, cs.select(t, j), cs.select(t, j + 1)))
     t0 = time.perf_counter()
     host = _host_copy(t)
     del t
@@ -70,6 +79,13 @@ def test_brick16g_full_cube(cs):
     assert_counts_match(counts, want, "fused counts")
     assert_counts_match(counts2, want, "two-pass counts")
     assert int(want.sum()) == r.n
+    # quantiles: the interpolation (the oracle's, over the two voxels) of
+    # the voxels of ranks j and j + 1, each checked by counting
+    assert qn == ref.n_valid
+    for (j, f, a, b), got in zip(qpairs, qv):
+        assert got == oracle.quantiles(np.array([a, b], np.float32), [f])[0]
+        for rank, v in ((j, a), (j + 1, b)):
+            assert int(np.count_nonzero(host < v)) <= rank < int(np.count_nonzero(host <= v))
     # the read probe saw every voxel's bits
     assert probe == int(np.bitwise_or.reduce(host.view(np.uint32).reshape(-1)))
     # Selection at full size, by the rank property that fixes the k-th
