@@ -1,22 +1,25 @@
-// cube_quantile.hip -- exact quantiles of the valid voxels: several ranks
-// refined side by side, so that any number of levels costs the same three
-// reads of the cube as one (up to eight distinct leading key buckets; more
-// add one read per eight).  The median and quantiles are the paper's example
+// cube_quantile.hip -- exact quantiles of the valid voxels: every wanted
+// rank is refined side by side, so that any number of levels costs three or
+// four reads of the cube.  The median and quantiles are the paper's example
 // of a global, multi-pass task (Section 3).
 //
 // Each wanted rank is found in the 32-bit order key of the voxels (the key
-// orders like the value, -0 before +0) 12, 12 and 8 bits at a time, as in
-// cube_select.hip.  Here every pass keeps one histogram per distinct key
-// prefix still in play, side by side in LDS:
+// orders like the value, -0 before +0) a few bits at a time, as in
+// cube_select.hip, but every pass keeps one histogram per distinct key
+// prefix still in play, side by side in LDS (at most 128 KB):
 //   pass 0: one 4096-bin histogram of the top 12 key bits;
-//   pass 1: for up to 8 distinct top-12 buckets, a 4096-bin histogram each
-//           of the next 12 bits (a 4096-entry LDS table maps a voxel's top
-//           bits to its histogram, or to none);
-//   pass 2: for up to 128 distinct 24-bit prefixes, a 256-bin histogram each
-//           of the last 8 bits (the table, then a short list per top bucket).
-// The host reads each pass's counts back (a few hundred KB at most) and
-// chooses the next pass's prefixes.  A level q takes the voxels of ranks
-// j = floor(q (n - 1)) and j + 1 and interpolates between them in FP64.
+//   then, when the ranks fall in at most 8 distinct top buckets, 12 and 8
+//   more bits (up to 8 histograms of 4096 bins, then up to 128 of 256);
+//   otherwise 8, 8 and 4 more bits (up to 128 histograms of 256 bins, then
+//   128 of 256, then 128 of 16).
+// A voxel finds its histogram through a 4096-entry LDS table indexed by its
+// top 12 key bits: in the pass after the first the table gives the
+// histogram itself; later it gives the group of prefixes under that bucket,
+// which the voxel scans for its own (groups are short: the prefixes of the
+// wanted ranks under one 12-bit bucket).  The host reads each pass's
+// counts back (at most 256 KB) and chooses the next pass's prefixes.  A
+// level q takes the voxels of ranks j = floor(q (n - 1)) and j + 1 and
+// interpolates between them in FP64.
 #include <math.h>
 #include <string.h>
 
@@ -31,32 +34,36 @@ namespace cube {
 namespace {
 
 constexpr int Q_THREADS = 1024;
-constexpr int Q_MAX_SLOTS1 = 8;          // pass-1 histograms per read
-constexpr int Q_MAX_SLOTS2 = 2 * CUBE_MAX_QUANTILES;
+constexpr int Q_MAX_SLOTS = 2 * CUBE_MAX_QUANTILES;   // distinct prefixes per pass
 constexpr size_t Q_LDS_HIST = 128 * 1024;
-constexpr int Q_ACC = 32768;             // max(8 * 4096, 128 * 256) counters
+constexpr int Q_ACC = 32768;             // slots * bins never exceeds this
 
 struct QuantArgs {
     Geom g;
-    int32_t pass;
-    int32_t nbins;                 // bins per histogram: 4096 or 256
-    int32_t slots;                 // histograms in this pass
+    int32_t shift, width;          // this pass bins key bits [shift, shift + width)
+    int32_t slots;                 // histograms (prefixes) in this pass
+    int32_t groups;                // top-12 buckets among the prefixes
     int32_t copies_log2;           // LDS copies of each histogram
-    int32_t slots1;                // pass 2: top buckets in the table
-    const short *top;              // passes 1, 2: top-12 bucket -> slot (-1: none)
-    const unsigned short *off;     // pass 2: slot1 s -> mids [off[s], off[s + 1])
-    const unsigned short *mids;    // pass 2: middle 12 bits of each 24-bit prefix
-    unsigned long long *acc;       // slots * nbins counters, zero on entry
+    const short *top;              // top-12 bucket -> group (-1: none)
+    const unsigned short *off;     // group g -> prefixes [off[g], off[g + 1])
+    const unsigned int *pre;       // the prefixes (key >> (shift + width)), ascending
+    unsigned long long *acc;       // slots << width counters, zero on entry
     unsigned long long *n_valid;   // pass 0: valid voxels, zero on entry
 };
 
-template <int PASS>
+// Pass modes: the first pass (no prefix), a pass whose prefixes are the top
+// 12 bits (the table gives the histogram), a pass with longer prefixes.
+enum { Q_FIRST = 0, Q_DIRECT = 1, Q_SCAN = 2 };
+
+template <int MODE>
 struct QuantStep {
     unsigned int *lds;
     const short *top;
-    const unsigned short *off, *mids;
-    int clog, cbase;
-    unsigned int valid;            // pass 0: valid voxels seen by this wavefront
+    const unsigned short *off;
+    const unsigned int *pre;
+    int shift, pshift, clog, cbase;
+    unsigned int bmask;
+    unsigned int valid;            // first pass: valid voxels seen by this wavefront
 
     template <int NV>
     __device__ __forceinline__ void operator()(const float (&x)[NV])
@@ -65,21 +72,25 @@ struct QuantStep {
         for (int j = 0; j < NV; ++j) {
             const float v = x[j];
             const bool ok = v == v;
-            if (PASS == 0) valid += (unsigned int)__popcll(__builtin_amdgcn_ballot_w64(ok));
+            if (MODE == Q_FIRST)
+                valid += (unsigned int)__popcll(__builtin_amdgcn_ballot_w64(ok));
             const unsigned int k = order_key(v);
             int idx = -1;
             if (ok) {
-                if (PASS == 0) {
+                if (MODE == Q_FIRST) {
                     idx = (int)(k >> 20);
-                } else if (PASS == 1) {
-                    const int s = top[k >> 20];
-                    if (s >= 0) idx = (s << 12) | (int)((k >> 8) & 0xfffu);
                 } else {
-                    const int s = top[k >> 20];
-                    if (s >= 0) {
-                        const unsigned short mid = (unsigned short)((k >> 8) & 0xfffu);
-                        for (int t = off[s]; t < off[s + 1]; ++t)
-                            if (mids[t] == mid) idx = (t << 8) | (int)(k & 0xffu);
+                    const int g = top[k >> 20];
+                    if (MODE == Q_DIRECT) {
+                        if (g >= 0)
+                            idx = (int)(((unsigned int)g << (pshift - shift)) |
+                                        ((k >> shift) & bmask));
+                    } else if (g >= 0) {
+                        const unsigned int p = k >> pshift;
+                        for (int t = off[g]; t < off[g + 1]; ++t)
+                            if (pre[t] == p)
+                                idx = (int)(((unsigned int)t << (pshift - shift)) |
+                                            ((k >> shift) & bmask));
                     }
                 }
             }
@@ -88,44 +99,49 @@ struct QuantStep {
     }
 };
 
-template <int PASS>
+template <int MODE>
 __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
 {
     extern __shared__ unsigned int lds[];
     __shared__ short s_top[4096];
-    __shared__ unsigned short s_off[Q_MAX_SLOTS2 + 1], s_mids[Q_MAX_SLOTS2];
+    __shared__ unsigned short s_off[Q_MAX_SLOTS + 1];
+    __shared__ unsigned int s_pre[Q_MAX_SLOTS];
     __shared__ unsigned int s_valid;
     const int tid = threadIdx.x, B = blockDim.x;
-    const int words = (a.slots * a.nbins) << a.copies_log2;
+    const int nbins = 1 << a.width;
+    const int words = (a.slots * nbins) << a.copies_log2;
     for (int i = tid; i < words; i += B) lds[i] = 0u;
-    if (PASS > 0)
+    if (MODE != Q_FIRST) {
         for (int i = tid; i < 4096; i += B) s_top[i] = a.top[i];
-    if (PASS == 2) {
-        for (int i = tid; i <= a.slots1; i += B) s_off[i] = a.off[i];
-        for (int i = tid; i < a.slots; i += B) s_mids[i] = a.mids[i];
+        for (int i = tid; i <= a.groups; i += B) s_off[i] = a.off[i];
+        for (int i = tid; i < a.slots; i += B) s_pre[i] = a.pre[i];
     }
     if (tid == 0) s_valid = 0u;
     __syncthreads();
 
-    QuantStep<PASS> st;
+    QuantStep<MODE> st;
     st.lds = lds;
     st.top = s_top;
     st.off = s_off;
-    st.mids = s_mids;
+    st.pre = s_pre;
+    st.shift = a.shift;
+    st.pshift = a.shift + a.width;
+    st.bmask = (unsigned int)nbins - 1u;
     st.clog = a.copies_log2;
     st.cbase = tid & 63 & ((1 << a.copies_log2) - 1);
     st.valid = 0u;
     scan_box(a.g, st);
     // Every lane of a wavefront holds the same count (sums of ballots).
-    if (PASS == 0 && (tid & 63) == 0 && st.valid) atomicAdd(&s_valid, st.valid);
+    if (MODE == Q_FIRST && (tid & 63) == 0 && st.valid) atomicAdd(&s_valid, st.valid);
     __syncthreads();
     const int C = 1 << a.copies_log2;
-    for (int b = tid; b < a.slots * a.nbins; b += B) {
+    for (int b = tid; b < a.slots * nbins; b += B) {
         unsigned int sum = 0;
         for (int c = 0; c < C; ++c) sum += lds[(b << a.copies_log2) + c];
         if (sum) atomicAdd(&a.acc[b], (unsigned long long)sum);
     }
-    if (PASS == 0 && tid == 0 && s_valid) atomicAdd(a.n_valid, (unsigned long long)s_valid);
+    if (MODE == Q_FIRST && tid == 0 && s_valid)
+        atomicAdd(a.n_valid, (unsigned long long)s_valid);
 }
 
 struct QuantWorkspace {
@@ -135,8 +151,10 @@ struct QuantWorkspace {
     short *h_tab = nullptr;               // pinned staging of the tables
 };
 
-constexpr size_t TAB_TOP = 4096, TAB_OFF = Q_MAX_SLOTS2 + 1, TAB_MIDS = Q_MAX_SLOTS2;
-constexpr size_t TAB_WORDS = TAB_TOP + TAB_OFF + TAB_MIDS;
+// Table layout (16-bit words): top[4096], off[Q_MAX_SLOTS + 1] (padded to an
+// even count), then pre[Q_MAX_SLOTS] as 32-bit words.
+constexpr size_t TAB_TOP = 4096, TAB_OFF = (Q_MAX_SLOTS + 2) & ~(size_t)1;
+constexpr size_t TAB_WORDS = TAB_TOP + TAB_OFF + 2 * Q_MAX_SLOTS;
 
 std::mutex g_qmu;
 QuantWorkspace g_qws[64];
@@ -162,17 +180,19 @@ int quant_ws(QuantWorkspace **out)
 }
 
 // One pass: zero the counters, upload the tables, launch, read the counters
-// back (slots * nbins of them, and the valid count after pass 0).  All on
-// the null stream; returns after the copy.
-int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int pass, int nbins, int slots,
-               size_t tab_words, int slots1 = 0)
+// back (slots << width of them, and the valid count after the first pass).
+// All on the null stream; returns after the copy.
+int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, bool first, int shift, int width,
+               int slots, int groups)
 {
     hipError_t e;
-    const size_t n = (size_t)slots * nbins;
+    const size_t n = (size_t)slots << width;
+    if (n > (size_t)Q_ACC || slots > Q_MAX_SLOTS || groups > Q_MAX_SLOTS)
+        return fail(CUBE_EINVAL, "quantile pass too large");
     if ((e = hipMemsetAsync(w->acc, 0, (Q_ACC + 1) * 8, nullptr)) != hipSuccess)
         return hip_fail(e, "quantile counters");
-    if (tab_words &&
-        (e = hipMemcpyAsync(w->tab, w->h_tab, tab_words * 2, hipMemcpyHostToDevice, nullptr)) !=
+    if (!first &&
+        (e = hipMemcpyAsync(w->tab, w->h_tab, TAB_WORDS * 2, hipMemcpyHostToDevice, nullptr)) !=
             hipSuccess)
         return hip_fail(e, "quantile tables");
     int clog = 0;
@@ -181,19 +201,20 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int pass, int nbins
     QuantArgs a;
     memset(&a, 0, sizeof a);
     a.g = g;
-    a.pass = pass;
-    a.nbins = nbins;
+    a.shift = shift;
+    a.width = width;
     a.slots = slots;
+    a.groups = groups;
     a.copies_log2 = clog;
-    a.slots1 = slots1;
     a.top = w->tab;
     a.off = (const unsigned short *)(w->tab + TAB_TOP);
-    a.mids = (const unsigned short *)(w->tab + TAB_TOP + TAB_OFF);
+    a.pre = (const unsigned int *)(w->tab + TAB_TOP + TAB_OFF);
     a.acc = w->acc;
     a.n_valid = w->acc + Q_ACC;
-    const void *k = pass == 0   ? reinterpret_cast<const void *>(&k_quant<0>)
-                    : pass == 1 ? reinterpret_cast<const void *>(&k_quant<1>)
-                                : reinterpret_cast<const void *>(&k_quant<2>);
+    // Prefixes of exactly the top 12 bits: the table gives the histogram.
+    const void *k = first                 ? reinterpret_cast<const void *>(&k_quant<Q_FIRST>)
+                    : shift + width == 20 ? reinterpret_cast<const void *>(&k_quant<Q_DIRECT>)
+                                          : reinterpret_cast<const void *>(&k_quant<Q_SCAN>);
     if (lds > 64 * 1024 &&
         (e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
             hipSuccess)
@@ -204,18 +225,18 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int pass, int nbins
         return hip_fail(e, "quantile launch");
     if ((e = hipMemcpyAsync(w->h_acc, w->acc, n * 8, hipMemcpyDeviceToHost, nullptr)) !=
             hipSuccess ||
-        (pass == 0 && (e = hipMemcpyAsync(w->h_acc + Q_ACC, w->acc + Q_ACC, 8,
-                                          hipMemcpyDeviceToHost, nullptr)) != hipSuccess) ||
+        (first && (e = hipMemcpyAsync(w->h_acc + Q_ACC, w->acc + Q_ACC, 8,
+                                      hipMemcpyDeviceToHost, nullptr)) != hipSuccess) ||
         (e = hipStreamSynchronize(nullptr)) != hipSuccess)
         return hip_fail(e, "quantile counts");
     return CUBE_OK;
 }
 
-// A rank being refined: the key bits found so far and the rank left inside
-// the current prefix.
+// A rank being refined: the key bits found so far (the prefix) and the
+// rank left inside that prefix.
 struct Want {
     unsigned long long rank;
-    unsigned int b0, b1, b2;
+    unsigned int prefix;
 };
 
 // The bin of `h` (nbins counters) holding rank r; r becomes the rank
@@ -253,8 +274,8 @@ int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t 
     Geom g;
     scan_geom(box, blocks, &g);
 
-    // Pass 0: the top 12 bits, and the valid count.
-    if ((rc = quant_pass(w, g, blocks, 0, 4096, 1, 0))) return rc;
+    // The top 12 bits, and the valid count.
+    if ((rc = quant_pass(w, g, blocks, true, 20, 12, 1, 0))) return rc;
     const unsigned long long n = w->h_acc[Q_ACC];
     if (n_valid_out) *n_valid_out = n;
     if (n == 0) return fail(CUBE_EINVAL, "no valid voxel");
@@ -272,55 +293,56 @@ int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t 
     std::vector<Want> want(ranks.size());
     for (size_t i = 0; i < ranks.size(); ++i) {
         want[i].rank = ranks[i];
-        want[i].b0 = pick_bin(w->h_acc, 4096, want[i].rank);
+        want[i].prefix = pick_bin(w->h_acc, 4096, want[i].rank);
     }
 
-    // Pass 1, eight top buckets per read: the middle 12 bits.
-    std::vector<unsigned int> tops;
-    for (const Want &x : want) tops.push_back(x.b0);
-    std::sort(tops.begin(), tops.end());
-    tops.erase(std::unique(tops.begin(), tops.end()), tops.end());
-    for (size_t r0 = 0; r0 < tops.size(); r0 += Q_MAX_SLOTS1) {
-        const int ns = (int)std::min(tops.size() - r0, (size_t)Q_MAX_SLOTS1);
-        for (size_t i = 0; i < TAB_TOP; ++i) w->h_tab[i] = -1;
-        for (int s = 0; s < ns; ++s) w->h_tab[tops[r0 + s]] = (short)s;
-        if ((rc = quant_pass(w, g, blocks, 1, 4096, ns, TAB_TOP))) return rc;
-        for (Want &x : want)
-            for (int s = 0; s < ns; ++s)
-                if (x.b0 == tops[r0 + s]) x.b1 = pick_bin(w->h_acc + (size_t)s * 4096, 4096, x.rank);
-    }
-
-    // Pass 2: the last 8 bits under each distinct 24-bit prefix, grouped by
-    // top bucket (slot1 = the bucket's index in `tops`).
+    // The remaining 20 bits: 12 + 8 when the ranks lie in at most 8 top
+    // buckets (a 4096-bin histogram per bucket fits), else 8 + 8 + 4.
     std::vector<unsigned int> pre;
-    for (const Want &x : want) pre.push_back((x.b0 << 12) | x.b1);
-    std::sort(pre.begin(), pre.end());
-    pre.erase(std::unique(pre.begin(), pre.end()), pre.end());
-    for (size_t i = 0; i < TAB_TOP; ++i) w->h_tab[i] = -1;
-    unsigned short *off = (unsigned short *)(w->h_tab + TAB_TOP);
-    unsigned short *mids = (unsigned short *)(w->h_tab + TAB_TOP + TAB_OFF);
-    size_t t = 0;
-    for (size_t s = 0; s < tops.size(); ++s) {
-        w->h_tab[tops[s]] = (short)s;
-        off[s] = (unsigned short)t;
-        while (t < pre.size() && (pre[t] >> 12) == tops[s]) {
-            mids[t] = (unsigned short)(pre[t] & 0xfffu);
-            ++t;
+    auto distinct = [&]() {
+        pre.clear();
+        for (const Want &x : want) pre.push_back(x.prefix);
+        std::sort(pre.begin(), pre.end());
+        pre.erase(std::unique(pre.begin(), pre.end()), pre.end());
+    };
+    distinct();
+    static const int wide[] = {12, 8}, narrow[] = {8, 8, 4};
+    const int *widths = pre.size() <= 8 ? wide : narrow;
+    const int npass = pre.size() <= 8 ? 2 : 3;
+    int done = 12;  // key bits found so far
+    for (int p = 0; p < npass; ++p) {
+        if (p) distinct();
+        const int width = widths[p];
+        const int shift = 32 - done - width;
+        // Tables: prefixes ascending, grouped by their top 12 bits.
+        short *top = w->h_tab;
+        unsigned short *off = (unsigned short *)(w->h_tab + TAB_TOP);
+        unsigned int *pv = (unsigned int *)(w->h_tab + TAB_TOP + TAB_OFF);
+        for (size_t i = 0; i < TAB_TOP; ++i) top[i] = -1;
+        int groups = 0;
+        for (size_t t = 0; t < pre.size(); ++t) {
+            const unsigned int t12 = pre[t] >> (done - 12);
+            if (t == 0 || t12 != (pre[t - 1] >> (done - 12))) {
+                top[t12] = (short)groups;
+                off[groups++] = (unsigned short)t;
+            }
+            pv[t] = pre[t];
         }
-    }
-    off[tops.size()] = (unsigned short)t;
-    if ((rc = quant_pass(w, g, blocks, 2, 256, (int)pre.size(), TAB_WORDS, (int)tops.size())))
-        return rc;
-    for (Want &x : want) {
-        const size_t slot = std::lower_bound(pre.begin(), pre.end(), (x.b0 << 12) | x.b1) -
-                            pre.begin();
-        x.b2 = pick_bin(w->h_acc + slot * 256, 256, x.rank);
+        off[groups] = (unsigned short)pre.size();
+        if ((rc = quant_pass(w, g, blocks, false, shift, width, (int)pre.size(), groups)))
+            return rc;
+        for (Want &x : want) {
+            const size_t slot = std::lower_bound(pre.begin(), pre.end(), x.prefix) - pre.begin();
+            const unsigned int b = pick_bin(w->h_acc + (slot << width), 1 << width, x.rank);
+            x.prefix = (x.prefix << width) | b;
+        }
+        done += width;
     }
 
     // The levels: the voxels of ranks j and j + 1, interpolated.
     auto value_of = [&](unsigned long long r) {
         const size_t i = std::lower_bound(ranks.begin(), ranks.end(), r) - ranks.begin();
-        return (double)key_to_float((want[i].b0 << 20) | (want[i].b1 << 8) | want[i].b2);
+        return (double)key_to_float(want[i].prefix);
     };
     for (int i = 0; i < m; ++i) {
         const double h = q[i] * (double)(n - 1);

@@ -54,6 +54,28 @@ def test_many_leading_buckets(cs):
     assert same(got, oracle.quantiles(a, levels))
 
 
+@pytest.mark.parametrize("groups", [1, 8, 9, 64])
+def test_bucket_count_boundary(cs, groups):
+    """Clusters [2^e, 1.1 * 2^e) of 1000 voxels each (e = 0..59 positive,
+    then negative ones) lie in top key buckets of their own, and one level
+    falls inside each sorted cluster: up to 8 buckets take the 12 + 12 +
+    8-bit passes, more the 12 + 8 + 8 + 4-bit ones."""
+    rng = np.random.default_rng(groups)
+    per = 1000
+    parts = []
+    for g in range(groups):
+        sign = 1.0 if g < 60 else -1.0
+        parts.append(sign * 2.0 ** (g % 60) * (1 + 0.1 * rng.random(per)))
+    a = np.concatenate(parts).astype(np.float32)
+    rng.shuffle(a)
+    n = a.size
+    levels = [(g * per + per // 2 + 0.37) / (n - 1) for g in range(groups)]
+    t = torch.from_numpy(a.reshape(groups, 1, per)).cuda()
+    got, nv = cs.quantiles(t, levels)
+    assert nv == n
+    assert same(got, oracle.quantiles(a, levels))
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 2), (3, 1, 1), (7, 5, 301), (64, 64, 128)])
 def test_shapes(cs, shape):
     rng = np.random.default_rng(sum(shape))
