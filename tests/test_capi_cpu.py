@@ -129,3 +129,26 @@ def test_tuning_table_round_trip(tmp_path):
             cs.cube_tune_load(str(tmp_path / "missing.json"))
     finally:
         cs.cube_tune_clear()
+
+
+@pytest.mark.parametrize("q,why", [([], "m=0"), ([0.5] * 65, "m=65"), ([1.5], "outside [0, 1]"),
+                                   ([-0.25], "outside [0, 1]"), ([math.nan], "outside [0, 1]")])
+def test_bad_quantile_levels_rejected_before_gpu(q, why):
+    code, msg = _code(cs.cube_quantiles, 0x1000, [4, 4, 4, 0, 0], q)
+    assert code == cs.CUBE_EINVAL and why in msg
+
+
+def test_quantile_and_probe_boxes_rejected_before_gpu():
+    code, msg = _code(cs.cube_quantiles, 0, [4, 4, 4, 0, 0], [0.5])
+    assert code == cs.CUBE_EINVAL and "NULL" in msg
+    code, msg = _code(cs.cube_quantiles, 0x1000, [8, 4, 4, 7, 0], [0.5])
+    assert code == cs.CUBE_EINVAL and "row pitch" in msg
+    for nbins, why in ((0, "nbins"), (65537, "nbins")):
+        code, msg = _code(cs.cube_read_probe, 0x1000, [4, 4, 4, 0, 0], nbins, 0x2000)
+        assert code == cs.CUBE_EINVAL and why in msg
+    code, msg = _code(cs.cube_read_probe, 0x1000, [4, 4, 4, 0, 0], 16, 0)
+    assert code == cs.CUBE_EINVAL and "NULL" in msg
+    code, msg = _code(cs.cube_read_probe, 0x1000, [4, 4, 4, 0, 0], 16, 0x2002)
+    assert code == cs.CUBE_EINVAL and "aligned" in msg
+    code, msg = _code(cs.cube_read_probe, 0, [4, 4, 4, 0, 0], 16, 0x2000)
+    assert code == cs.CUBE_EINVAL and "NULL" in msg
