@@ -293,8 +293,8 @@ __device__ Summary<T> merge_records(const WaveRec *recs, int n_recs)
     return t;
 }
 
-// One tile: U float4 loads per lane, lane stride B; uniform base + fixed
-// per-lane 32-bit byte offsets, so the loads use scalar-base addressing.
+// One tile: U float4 loads per lane, lane stride B (a wavefront reads 1 KB
+// per load); a uniform base plus fixed per-lane 32-bit byte offsets.
 template <int U>
 __device__ __forceinline__ void load_tile(f4 (&v)[U], const f4 *q4, long long off, int B, int tid)
 {
