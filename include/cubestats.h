@@ -207,9 +207,9 @@ CUBE_API int cube_median(const float *ptr, const int64_t *dims, double *median,
  * b = +Inf) and -Inf to +Inf gives NaN.  At q = 1/2 this is the median up to
  * rounding: cube_median averages (a + b) / 2 instead.
  * Results go to out[0..m-1] (host), the valid count to *n_valid (host; may
- * be NULL).  Three reads of the box when the ranks wanted fall in at most
- * eight distinct leading 12-bit key buckets, four otherwise; synchronous on
- * the null stream.  Keeps about 300 KB of device and
+ * be NULL).  Three reads of the box when the ranks wanted (two per level at
+ * most) fall in at most eight distinct leading 12-bit key buckets and number
+ * at most 96, four otherwise; synchronous on the null stream.  Keeps about 300 KB of device and
  * pinned host memory per device until cube_shutdown.  Errors: CUBE_EINVAL
  * for the box errors of the other calls, an empty box, no valid voxel (with
  * *n_valid = 0), NULL q or out, m outside its range or a level outside

@@ -6,20 +6,21 @@
 // Each wanted rank is found in the 32-bit order key of the voxels (the key
 // orders like the value, -0 before +0) a few bits at a time, as in
 // cube_select.hip, but every pass keeps one histogram per distinct key
-// prefix still in play, side by side in LDS (at most 128 KB):
+// prefix still in play, side by side in LDS:
 //   pass 0: one 4096-bin histogram of the top 12 key bits;
-//   then, when the ranks fall in at most 8 distinct top buckets, 12 and 8
-//   more bits (up to 8 histograms of 4096 bins, then up to 128 of 256);
-//   otherwise 8, 8 and 4 more bits (up to 128 histograms of 256 bins, then
-//   128 of 256, then 128 of 16).
-// A voxel finds its histogram through a 4096-entry LDS table indexed by its
-// top 12 key bits: in the pass after the first the table gives the
-// histogram itself; later it gives the group of prefixes under that bucket,
-// which the voxel scans for its own (groups are short: the prefixes of the
-// wanted ranks under one 12-bit bucket).  The host reads each pass's
-// counts back (at most 256 KB) and chooses the next pass's prefixes.  A
-// level q takes the voxels of ranks j = floor(q (n - 1)) and j + 1 and
-// interpolates between them in FP64.
+//   then, when the ranks fall in at most 8 distinct top buckets and number
+//   at most 96, 12 and 8 more bits (up to 8 histograms of 4096 bins, then
+//   up to 96 of 256);
+//   otherwise 8, 6 and 6 more bits (up to 128 histograms of 256 bins, then
+//   128 of 64, then 128 of 64).
+// A voxel finds its histogram through a chain of direct-mapped LDS byte
+// tables, one per level of the prefix: the table of the top 12 key bits
+// gives the voxel's index among the wanted 12-bit prefixes (or -1), and
+// each further table, indexed by that index and the level's next key bits,
+// gives its index among the longer prefixes.  No search, no loop.  The host
+// reads each pass's counts back (at most 256 KB) and builds the next pass's
+// tables.  A level q takes the voxels of ranks j = floor(q (n - 1)) and
+// j + 1 and interpolates between them in FP64.
 #include <math.h>
 #include <string.h>
 
@@ -34,35 +35,31 @@ namespace cube {
 namespace {
 
 constexpr int Q_THREADS = 1024;
-constexpr int Q_MAX_SLOTS = 2 * CUBE_MAX_QUANTILES;   // distinct prefixes per pass
-constexpr size_t Q_LDS_HIST = 128 * 1024;
-constexpr int Q_ACC = 32768;             // slots * bins never exceeds this
+constexpr int Q_MAX_RANKS = 2 * CUBE_MAX_QUANTILES;   // so every table index fits int8
+constexpr size_t Q_LDS = 160 * 1024 - 256;  // dynamic LDS of one block, static aside
+constexpr int Q_ACC = 32768;                // slots << bin width never exceeds this
+constexpr size_t Q_TAB = 4096 + 32768 + 8192;  // bytes: T1, T2, T3 at most
 
 struct QuantArgs {
     Geom g;
     int32_t shift, width;          // this pass bins key bits [shift, shift + width)
+    int32_t w2, w3;                // bits of the second and third prefix levels
     int32_t slots;                 // histograms (prefixes) in this pass
-    int32_t groups;                // top-12 buckets among the prefixes
     int32_t copies_log2;           // LDS copies of each histogram
-    const short *top;              // top-12 bucket -> group (-1: none)
-    const unsigned short *off;     // group g -> prefixes [off[g], off[g + 1])
-    const unsigned int *pre;       // the prefixes (key >> (shift + width)), ascending
+    int32_t t2_bytes, t3_bytes;    // sizes of the second and third tables
+    const signed char *tab;        // T1 (4096 bytes), T2, T3, back to back
     unsigned long long *acc;       // slots << width counters, zero on entry
     unsigned long long *n_valid;   // pass 0: valid voxels, zero on entry
 };
 
-// Pass modes: the first pass (no prefix), a pass whose prefixes are the top
-// 12 bits (the table gives the histogram), a pass with longer prefixes.
-enum { Q_FIRST = 0, Q_DIRECT = 1, Q_SCAN = 2 };
-
-template <int MODE>
+// NL: prefix levels of this pass (0 for the first pass).
+template <int NL>
 struct QuantStep {
     unsigned int *lds;
-    const short *top;
-    const unsigned short *off;
-    const unsigned int *pre;
-    int shift, pshift, clog, cbase;
+    const signed char *t1, *t2, *t3;
+    int shift, w2, w3, clog, cbase;
     unsigned int bmask;
+    int wb;
     unsigned int valid;            // first pass: valid voxels seen by this wavefront
 
     template <int NV>
@@ -72,67 +69,67 @@ struct QuantStep {
         for (int j = 0; j < NV; ++j) {
             const float v = x[j];
             const bool ok = v == v;
-            if (MODE == Q_FIRST)
-                valid += (unsigned int)__popcll(__builtin_amdgcn_ballot_w64(ok));
+            if (NL == 0) valid += (unsigned int)__popcll(__builtin_amdgcn_ballot_w64(ok));
             const unsigned int k = order_key(v);
-            int idx = -1;
-            if (ok) {
-                if (MODE == Q_FIRST) {
-                    idx = (int)(k >> 20);
-                } else {
-                    const int g = top[k >> 20];
-                    if (MODE == Q_DIRECT) {
-                        if (g >= 0)
-                            idx = (int)(((unsigned int)g << (pshift - shift)) |
-                                        ((k >> shift) & bmask));
-                    } else if (g >= 0) {
-                        const unsigned int p = k >> pshift;
-                        for (int t = off[g]; t < off[g + 1]; ++t)
-                            if (pre[t] == p)
-                                idx = (int)(((unsigned int)t << (pshift - shift)) |
-                                            ((k >> shift) & bmask));
-                    }
+            int idx;
+            if (NL == 0) {
+                idx = (int)(k >> 20);
+            } else {
+                // The index among this pass's prefixes, level by level; a
+                // voxel outside them carries -1 (the table reads use index 0
+                // then, and their results are dropped).
+                int g = t1[k >> 20];
+                if (NL >= 2) {
+                    const unsigned int b2 = (k >> (20 - w2)) & ((1u << w2) - 1u);
+                    const int r = t2[((unsigned int)max(g, 0) << w2) | b2];
+                    g = g >= 0 ? r : -1;
                 }
+                if (NL >= 3) {
+                    const unsigned int b3 = (k >> (20 - w2 - w3)) & ((1u << w3) - 1u);
+                    const int r = t3[((unsigned int)max(g, 0) << w3) | b3];
+                    g = g >= 0 ? r : -1;
+                }
+                idx = g >= 0 ? (int)(((unsigned int)g << wb) | ((k >> shift) & bmask)) : -1;
             }
-            if (idx >= 0) atomicAdd(&lds[(idx << clog) + cbase], 1u);
+            if (ok && idx >= 0) atomicAdd(&lds[(idx << clog) + cbase], 1u);
         }
     }
 };
 
-template <int MODE>
+template <int NL>
 __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
 {
     extern __shared__ unsigned int lds[];
-    __shared__ short s_top[4096];
-    __shared__ unsigned short s_off[Q_MAX_SLOTS + 1];
-    __shared__ unsigned int s_pre[Q_MAX_SLOTS];
     __shared__ unsigned int s_valid;
     const int tid = threadIdx.x, B = blockDim.x;
     const int nbins = 1 << a.width;
     const int words = (a.slots * nbins) << a.copies_log2;
     for (int i = tid; i < words; i += B) lds[i] = 0u;
-    if (MODE != Q_FIRST) {
-        for (int i = tid; i < 4096; i += B) s_top[i] = a.top[i];
-        for (int i = tid; i <= a.groups; i += B) s_off[i] = a.off[i];
-        for (int i = tid; i < a.slots; i += B) s_pre[i] = a.pre[i];
-    }
+    // The tables follow the histograms in LDS (all sizes are multiples of 4).
+    unsigned int *tw = lds + words;
+    const int tab_words = NL == 0 ? 0 : (4096 + (NL >= 2 ? a.t2_bytes : 0) +
+                                         (NL >= 3 ? a.t3_bytes : 0)) / 4;
+    const unsigned int *src = (const unsigned int *)a.tab;
+    for (int i = tid; i < tab_words; i += B) tw[i] = src[i];
     if (tid == 0) s_valid = 0u;
     __syncthreads();
 
-    QuantStep<MODE> st;
+    QuantStep<NL> st;
     st.lds = lds;
-    st.top = s_top;
-    st.off = s_off;
-    st.pre = s_pre;
+    st.t1 = (const signed char *)tw;
+    st.t2 = st.t1 + 4096;
+    st.t3 = st.t2 + a.t2_bytes;
     st.shift = a.shift;
-    st.pshift = a.shift + a.width;
+    st.w2 = a.w2;
+    st.w3 = a.w3;
+    st.wb = a.width;
     st.bmask = (unsigned int)nbins - 1u;
     st.clog = a.copies_log2;
     st.cbase = tid & 63 & ((1 << a.copies_log2) - 1);
     st.valid = 0u;
     scan_box(a.g, st);
     // Every lane of a wavefront holds the same count (sums of ballots).
-    if (MODE == Q_FIRST && (tid & 63) == 0 && st.valid) atomicAdd(&s_valid, st.valid);
+    if (NL == 0 && (tid & 63) == 0 && st.valid) atomicAdd(&s_valid, st.valid);
     __syncthreads();
     const int C = 1 << a.copies_log2;
     for (int b = tid; b < a.slots * nbins; b += B) {
@@ -140,21 +137,15 @@ __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
         for (int c = 0; c < C; ++c) sum += lds[(b << a.copies_log2) + c];
         if (sum) atomicAdd(&a.acc[b], (unsigned long long)sum);
     }
-    if (MODE == Q_FIRST && tid == 0 && s_valid)
-        atomicAdd(a.n_valid, (unsigned long long)s_valid);
+    if (NL == 0 && tid == 0 && s_valid) atomicAdd(a.n_valid, (unsigned long long)s_valid);
 }
 
 struct QuantWorkspace {
     unsigned long long *acc = nullptr;    // Q_ACC counters + 1 valid counter
-    short *tab = nullptr;                 // top table, offsets, mids
+    signed char *tab = nullptr;           // the prefix tables
     unsigned long long *h_acc = nullptr;  // pinned copy of the counters
-    short *h_tab = nullptr;               // pinned staging of the tables
+    signed char *h_tab = nullptr;         // pinned staging of the tables
 };
-
-// Table layout (16-bit words): top[4096], off[Q_MAX_SLOTS + 1] (padded to an
-// even count), then pre[Q_MAX_SLOTS] as 32-bit words.
-constexpr size_t TAB_TOP = 4096, TAB_OFF = (Q_MAX_SLOTS + 2) & ~(size_t)1;
-constexpr size_t TAB_WORDS = TAB_TOP + TAB_OFF + 2 * Q_MAX_SLOTS;
 
 std::mutex g_qmu;
 QuantWorkspace g_qws[64];
@@ -169,9 +160,9 @@ int quant_ws(QuantWorkspace **out)
         QuantWorkspace &w = g_qws[dev];
         hipError_t e;
         if ((e = hipMalloc(&w.acc, (Q_ACC + 1) * 8)) != hipSuccess ||
-            (e = hipMalloc(&w.tab, TAB_WORDS * 2)) != hipSuccess ||
+            (e = hipMalloc(&w.tab, Q_TAB)) != hipSuccess ||
             (e = hipHostMalloc(&w.h_acc, (Q_ACC + 1) * 8)) != hipSuccess ||
-            (e = hipHostMalloc(&w.h_tab, TAB_WORDS * 2)) != hipSuccess)
+            (e = hipHostMalloc(&w.h_tab, Q_TAB)) != hipSuccess)
             return hip_fail(e, "quantile workspace");
         g_qws_ready[dev] = true;
     }
@@ -179,42 +170,45 @@ int quant_ws(QuantWorkspace **out)
     return CUBE_OK;
 }
 
-// One pass: zero the counters, upload the tables, launch, read the counters
-// back (slots << width of them, and the valid count after the first pass).
-// All on the null stream; returns after the copy.
-int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, bool first, int shift, int width,
-               int slots, int groups)
+// One pass: zero the counters, upload the tables (already staged in h_tab),
+// launch, read the counters back (slots << width of them, and the valid
+// count after the first pass).  All on the null stream; returns after the
+// copy.  nl: prefix levels (0 for the first pass); w2, w3 their widths.
+int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, int width,
+               int w2, int w3, int slots, int t2_bytes, int t3_bytes)
 {
     hipError_t e;
     const size_t n = (size_t)slots << width;
-    if (n > (size_t)Q_ACC || slots > Q_MAX_SLOTS || groups > Q_MAX_SLOTS)
+    const size_t tab = nl == 0 ? 0 : 4096 + (nl >= 2 ? t2_bytes : 0) + (nl >= 3 ? t3_bytes : 0);
+    if (n > (size_t)Q_ACC || slots > Q_MAX_RANKS || tab > Q_TAB || n * 4 + tab > Q_LDS)
         return fail(CUBE_EINVAL, "quantile pass too large");
     if ((e = hipMemsetAsync(w->acc, 0, (Q_ACC + 1) * 8, nullptr)) != hipSuccess)
         return hip_fail(e, "quantile counters");
-    if (!first &&
-        (e = hipMemcpyAsync(w->tab, w->h_tab, TAB_WORDS * 2, hipMemcpyHostToDevice, nullptr)) !=
-            hipSuccess)
+    if (tab &&
+        (e = hipMemcpyAsync(w->tab, w->h_tab, tab, hipMemcpyHostToDevice, nullptr)) != hipSuccess)
         return hip_fail(e, "quantile tables");
+    // Up to eight copies of each histogram, as many as fit beside the tables.
     int clog = 0;
-    while (clog < 3 && (n << (clog + 1)) * 4 <= Q_LDS_HIST) ++clog;
-    const size_t lds = (n << clog) * 4;
+    while (clog < 3 && (n << (clog + 1)) * 4 + tab <= Q_LDS) ++clog;
+    const size_t lds = (n << clog) * 4 + tab;
     QuantArgs a;
     memset(&a, 0, sizeof a);
     a.g = g;
     a.shift = shift;
     a.width = width;
+    a.w2 = w2;
+    a.w3 = w3;
     a.slots = slots;
-    a.groups = groups;
     a.copies_log2 = clog;
-    a.top = w->tab;
-    a.off = (const unsigned short *)(w->tab + TAB_TOP);
-    a.pre = (const unsigned int *)(w->tab + TAB_TOP + TAB_OFF);
+    a.t2_bytes = t2_bytes;
+    a.t3_bytes = t3_bytes;
+    a.tab = w->tab;
     a.acc = w->acc;
     a.n_valid = w->acc + Q_ACC;
-    // Prefixes of exactly the top 12 bits: the table gives the histogram.
-    const void *k = first                 ? reinterpret_cast<const void *>(&k_quant<Q_FIRST>)
-                    : shift + width == 20 ? reinterpret_cast<const void *>(&k_quant<Q_DIRECT>)
-                                          : reinterpret_cast<const void *>(&k_quant<Q_SCAN>);
+    const void *k = nl == 0   ? reinterpret_cast<const void *>(&k_quant<0>)
+                    : nl == 1 ? reinterpret_cast<const void *>(&k_quant<1>)
+                    : nl == 2 ? reinterpret_cast<const void *>(&k_quant<2>)
+                              : reinterpret_cast<const void *>(&k_quant<3>);
     if (lds > 64 * 1024 &&
         (e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
             hipSuccess)
@@ -225,18 +219,18 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, bool first, int shi
         return hip_fail(e, "quantile launch");
     if ((e = hipMemcpyAsync(w->h_acc, w->acc, n * 8, hipMemcpyDeviceToHost, nullptr)) !=
             hipSuccess ||
-        (first && (e = hipMemcpyAsync(w->h_acc + Q_ACC, w->acc + Q_ACC, 8,
-                                      hipMemcpyDeviceToHost, nullptr)) != hipSuccess) ||
+        (nl == 0 && (e = hipMemcpyAsync(w->h_acc + Q_ACC, w->acc + Q_ACC, 8,
+                                        hipMemcpyDeviceToHost, nullptr)) != hipSuccess) ||
         (e = hipStreamSynchronize(nullptr)) != hipSuccess)
         return hip_fail(e, "quantile counts");
     return CUBE_OK;
 }
 
-// A rank being refined: the key bits found so far (the prefix) and the
-// rank left inside that prefix.
+// A rank being refined: the key bits found so far (at the top of `key`) and
+// the rank left inside that prefix.
 struct Want {
     unsigned long long rank;
-    unsigned int prefix;
+    unsigned int key;
 };
 
 // The bin of `h` (nbins counters) holding rank r; r becomes the rank
@@ -265,6 +259,27 @@ double interpolate(double a, double b, double f)
     return a + f * (b - a);
 }
 
+// The distinct values of the top `bits` key bits among the wanted ranks,
+// ascending.
+std::vector<unsigned int> prefixes(const std::vector<Want> &want, int bits)
+{
+    std::vector<unsigned int> p;
+    for (const Want &x : want) p.push_back(x.key >> (32 - bits));
+    std::sort(p.begin(), p.end());
+    p.erase(std::unique(p.begin(), p.end()), p.end());
+    return p;
+}
+
+size_t index_of(const std::vector<unsigned int> &p, unsigned int v)
+{
+    return std::lower_bound(p.begin(), p.end(), v) - p.begin();
+}
+
+size_t index_of_rank(const std::vector<unsigned long long> &r, unsigned long long v)
+{
+    return std::lower_bound(r.begin(), r.end(), v) - r.begin();
+}
+
 int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t *n_valid_out)
 {
     QuantWorkspace *w = nullptr;
@@ -275,12 +290,12 @@ int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t 
     scan_geom(box, blocks, &g);
 
     // The top 12 bits, and the valid count.
-    if ((rc = quant_pass(w, g, blocks, true, 20, 12, 1, 0))) return rc;
+    if ((rc = quant_pass(w, g, blocks, 0, 20, 12, 0, 0, 1, 0, 0))) return rc;
     const unsigned long long n = w->h_acc[Q_ACC];
     if (n_valid_out) *n_valid_out = n;
     if (n == 0) return fail(CUBE_EINVAL, "no valid voxel");
 
-    // The ranks the levels need, ascending and distinct.
+    // The ranks the levels need, ascending and distinct (at most 2m).
     std::vector<unsigned long long> ranks;
     for (int i = 0; i < m; ++i) {
         const double h = q[i] * (double)(n - 1);
@@ -293,56 +308,70 @@ int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t 
     std::vector<Want> want(ranks.size());
     for (size_t i = 0; i < ranks.size(); ++i) {
         want[i].rank = ranks[i];
-        want[i].prefix = pick_bin(w->h_acc, 4096, want[i].rank);
+        want[i].key = pick_bin(w->h_acc, 4096, want[i].rank) << 20;
     }
 
     // The remaining 20 bits: 12 + 8 when the ranks lie in at most 8 top
-    // buckets (a 4096-bin histogram per bucket fits), else 8 + 8 + 4.
-    std::vector<unsigned int> pre;
-    auto distinct = [&]() {
-        pre.clear();
-        for (const Want &x : want) pre.push_back(x.prefix);
-        std::sort(pre.begin(), pre.end());
-        pre.erase(std::unique(pre.begin(), pre.end()), pre.end());
-    };
-    distinct();
-    static const int wide[] = {12, 8}, narrow[] = {8, 8, 4};
-    const int *widths = pre.size() <= 8 ? wide : narrow;
-    const int npass = pre.size() <= 8 ? 2 : 3;
-    int done = 12;  // key bits found so far
+    // buckets and number at most 96 (the tables and histograms of both
+    // passes fit in LDS), else 8 + 6 + 6.
+    const bool wide = prefixes(want, 12).size() <= 8 && want.size() <= 96;
+    static const int wide_w[] = {12, 8}, narrow_w[] = {8, 6, 6};
+    const int *widths = wide ? wide_w : narrow_w;
+    const int npass = wide ? 2 : 3;
+    int lev[3] = {12, 0, 0};  // widths of the prefix levels
+    int done = 12;            // key bits found so far
     for (int p = 0; p < npass; ++p) {
-        if (p) distinct();
+        const int nl = p + 1;  // prefix levels of this pass
         const int width = widths[p];
-        const int shift = 32 - done - width;
-        // Tables: prefixes ascending, grouped by their top 12 bits.
-        short *top = w->h_tab;
-        unsigned short *off = (unsigned short *)(w->h_tab + TAB_TOP);
-        unsigned int *pv = (unsigned int *)(w->h_tab + TAB_TOP + TAB_OFF);
-        for (size_t i = 0; i < TAB_TOP; ++i) top[i] = -1;
-        int groups = 0;
-        for (size_t t = 0; t < pre.size(); ++t) {
-            const unsigned int t12 = pre[t] >> (done - 12);
-            if (t == 0 || t12 != (pre[t - 1] >> (done - 12))) {
-                top[t12] = (short)groups;
-                off[groups++] = (unsigned short)t;
+        // Level tables: T1 maps the top 12 bits to the index among the
+        // 12-bit prefixes; T2 maps (that index, the next lev[1] bits) to the
+        // index among the longer prefixes; T3 likewise one level further.
+        signed char *t1 = w->h_tab;
+        memset(t1, -1, 4096);
+        const std::vector<unsigned int> p1 = prefixes(want, 12);
+        for (size_t i = 0; i < p1.size(); ++i) t1[p1[i]] = (signed char)i;
+        std::vector<unsigned int> deepest = p1;
+        int t2_bytes = 0, t3_bytes = 0;
+        if (nl >= 2) {
+            const std::vector<unsigned int> p2 = prefixes(want, 12 + lev[1]);
+            signed char *t2 = t1 + 4096;
+            t2_bytes = (int)(p1.size() << lev[1]);
+            memset(t2, -1, (size_t)t2_bytes);
+            for (size_t i = 0; i < p2.size(); ++i) {
+                const unsigned int hi = (unsigned int)index_of(p1, p2[i] >> lev[1]);
+                t2[(hi << lev[1]) | (p2[i] & ((1u << lev[1]) - 1u))] = (signed char)i;
             }
-            pv[t] = pre[t];
+            if (nl >= 3) {
+                const std::vector<unsigned int> p3 = prefixes(want, 12 + lev[1] + lev[2]);
+                signed char *t3 = t2 + t2_bytes;
+                t3_bytes = (int)(p2.size() << lev[2]);
+                memset(t3, -1, (size_t)t3_bytes);
+                for (size_t i = 0; i < p3.size(); ++i) {
+                    const unsigned int hi = (unsigned int)index_of(p2, p3[i] >> lev[2]);
+                    t3[(hi << lev[2]) | (p3[i] & ((1u << lev[2]) - 1u))] = (signed char)i;
+                }
+                deepest = p3;
+            } else {
+                deepest = p2;
+            }
         }
-        off[groups] = (unsigned short)pre.size();
-        if ((rc = quant_pass(w, g, blocks, false, shift, width, (int)pre.size(), groups)))
+        const int shift = 32 - done - width;
+        if ((rc = quant_pass(w, g, blocks, nl, shift, width, lev[1], lev[2], (int)deepest.size(),
+                             t2_bytes, t3_bytes)))
             return rc;
         for (Want &x : want) {
-            const size_t slot = std::lower_bound(pre.begin(), pre.end(), x.prefix) - pre.begin();
-            const unsigned int b = pick_bin(w->h_acc + (slot << width), 1 << width, x.rank);
-            x.prefix = (x.prefix << width) | b;
+            const size_t slot = index_of(deepest, x.key >> (32 - done));
+            const unsigned int b =
+                pick_bin(w->h_acc + (slot << width), 1 << width, x.rank);
+            x.key |= b << shift;
         }
+        if (nl < 3) lev[nl] = width;
         done += width;
     }
 
     // The levels: the voxels of ranks j and j + 1, interpolated.
     auto value_of = [&](unsigned long long r) {
-        const size_t i = std::lower_bound(ranks.begin(), ranks.end(), r) - ranks.begin();
-        return (double)key_to_float(want[i].prefix);
+        return (double)key_to_float(want[index_of_rank(ranks, r)].key);
     };
     for (int i = 0; i < m; ++i) {
         const double h = q[i] * (double)(n - 1);
