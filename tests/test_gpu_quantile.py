@@ -59,7 +59,7 @@ def test_bucket_count_boundary(cs, groups):
     """Clusters [2^e, 1.1 * 2^e) of 1000 voxels each (e = 0..59 positive,
     then negative ones) lie in top key buckets of their own, and one level
     falls inside each sorted cluster: up to 8 buckets take the 12 + 12 +
-    8-bit passes, more the 12 + 8 + 8 + 4-bit ones."""
+    8-bit passes, more the 12 + 8 + 6 + 6-bit ones."""
     rng = np.random.default_rng(groups)
     per = 1000
     parts = []
@@ -73,6 +73,22 @@ def test_bucket_count_boundary(cs, groups):
     t = torch.from_numpy(a.reshape(groups, 1, per)).cuda()
     got, nv = cs.quantiles(t, levels)
     assert nv == n
+    assert same(got, oracle.quantiles(a, levels))
+
+
+def test_many_ranks_in_few_buckets(cs):
+    """64 levels (up to 128 ranks) inside 4 top key buckets: more than 96
+    ranks take the 12 + 8 + 6 + 6-bit passes although few buckets are hit;
+    ties make some ranks share a key."""
+    rng = np.random.default_rng(41)
+    parts = [2.0 ** e * (1 + 0.1 * rng.random(50_000)) for e in (0, 3, 7, 11)]
+    a = np.concatenate(parts).astype(np.float32)
+    a[::97] = a[5]                                 # a run of equal keys
+    rng.shuffle(a)
+    levels = np.sort(rng.random(64))
+    t = torch.from_numpy(a.reshape(4, 500, 100)).cuda()
+    got, nv = cs.quantiles(t, levels)
+    assert nv == a.size
     assert same(got, oracle.quantiles(a, levels))
 
 
