@@ -28,11 +28,11 @@ def compare(got, host, what):
     rmip, rmom0, rnv = oracle.project(host)
     assert np.array_equal(nv.view(np.uint32), rnv), what
     assert np.array_equal(mip.view(np.uint32), rmip.view(np.uint32)), what
-    with np.errstate(invalid="ignore"):
+    with np.errstate(invalid="ignore"):  # Inf - Inf where both maps hold the same Inf
         scale = np.nansum(np.abs(host.astype(np.float64)), axis=0).reshape(rmom0.shape)
+        close = np.abs(mom0 - rmom0) <= MOM0_TOL * scale
     both_nan = np.isnan(mom0) & np.isnan(rmom0)
     inf_equal = np.isinf(rmom0) & (mom0 == rmom0)
-    close = np.abs(mom0 - rmom0) <= MOM0_TOL * scale
     ok = both_nan | inf_equal | close
     assert ok.all(), (what, np.argwhere(~ok)[:5])
 
