@@ -14,13 +14,16 @@
 //   otherwise 8, 6 and 6 more bits (up to 128 histograms of 256 bins, then
 //   128 of 64, then 128 of 64).
 // A voxel finds its histogram through a chain of direct-mapped LDS byte
-// tables, one per level of the prefix: the table of the top 12 key bits
-// gives the voxel's index among the wanted 12-bit prefixes (or -1), and
-// each further table, indexed by that index and the level's next key bits,
-// gives its index among the longer prefixes.  No search, no loop.  The host
-// reads each pass's counts back (at most 256 KB) and builds the next pass's
-// tables.  A level q takes the voxels of ranks j = floor(q (n - 1)) and
-// j + 1 and interpolates between them in FP64.
+// tables, one per level of the prefix.  Entries hold index + 1 (0: none),
+// and row 0 of every further table is all zero, so a voxel outside the
+// wanted prefixes falls through to 0 with no test: the table of the top 12
+// key bits gives its index among the wanted 12-bit prefixes, each further
+// table, indexed by that entry and the level's next key bits, its index
+// among the longer prefixes.  Only voxels that end at a wanted prefix count
+// (histogram row 0 is laid out but never written).  No search.  The
+// host reads each pass's counts back (at most 256 KB) and builds the next
+// pass's tables.  A level q takes the voxels of ranks j = floor(q (n - 1))
+// and j + 1 and interpolates between them in FP64.
 #include <math.h>
 #include <string.h>
 
@@ -35,10 +38,10 @@ namespace cube {
 namespace {
 
 constexpr int Q_THREADS = 1024;
-constexpr int Q_MAX_RANKS = 2 * CUBE_MAX_QUANTILES;   // so every table index fits int8
+constexpr int Q_MAX_RANKS = 2 * CUBE_MAX_QUANTILES;   // index + 1 fits a byte
 constexpr size_t Q_LDS = 160 * 1024 - 256;  // dynamic LDS of one block, static aside
 constexpr int Q_ACC = 32768;                // slots << bin width never exceeds this
-constexpr size_t Q_TAB = 4096 + 32768 + 8192;  // bytes: T1, T2, T3 at most
+constexpr size_t Q_TAB = 4096 + 9 * 4096 + 129 * 64;  // bytes: T1, T2, T3 at most
 
 struct QuantArgs {
     Geom g;
@@ -47,7 +50,7 @@ struct QuantArgs {
     int32_t slots;                 // histograms (prefixes) in this pass
     int32_t copies_log2;           // LDS copies of each histogram
     int32_t t2_bytes, t3_bytes;    // sizes of the second and third tables
-    const signed char *tab;        // T1 (4096 bytes), T2, T3, back to back
+    const unsigned char *tab;      // T1 (4096 bytes), T2, T3, back to back
     unsigned long long *acc;       // slots << width counters, zero on entry
     unsigned long long *n_valid;   // pass 0: valid voxels, zero on entry
 };
@@ -56,7 +59,7 @@ struct QuantArgs {
 template <int NL>
 struct QuantStep {
     unsigned int *lds;
-    const signed char *t1, *t2, *t3;
+    const unsigned char *t1, *t2, *t3;
     int shift, w2, w3, clog, cbase;
     unsigned int bmask;
     int wb;
@@ -71,27 +74,17 @@ struct QuantStep {
             const bool ok = v == v;
             if (NL == 0) valid += (unsigned int)__popcll(__builtin_amdgcn_ballot_w64(ok));
             const unsigned int k = order_key(v);
-            int idx;
             if (NL == 0) {
-                idx = (int)(k >> 20);
+                // one histogram, blanks skipped (they are rare)
+                if (ok) atomicAdd(&lds[((k >> 20) << clog) + cbase], 1u);
             } else {
-                // The index among this pass's prefixes, level by level; a
-                // voxel outside them carries -1 (the table reads use index 0
-                // then, and their results are dropped).
-                int g = t1[k >> 20];
-                if (NL >= 2) {
-                    const unsigned int b2 = (k >> (20 - w2)) & ((1u << w2) - 1u);
-                    const int r = t2[((unsigned int)max(g, 0) << w2) | b2];
-                    g = g >= 0 ? r : -1;
-                }
-                if (NL >= 3) {
-                    const unsigned int b3 = (k >> (20 - w2 - w3)) & ((1u << w3) - 1u);
-                    const int r = t3[((unsigned int)max(g, 0) << w3) | b3];
-                    g = g >= 0 ? r : -1;
-                }
-                idx = g >= 0 ? (int)(((unsigned int)g << wb) | ((k >> shift) & bmask)) : -1;
+                // histogram row g: 0 (no wanted prefix) counts nothing
+                unsigned int g = t1[k >> 20];
+                if (NL >= 2) g = t2[(g << w2) | ((k >> (20 - w2)) & ((1u << w2) - 1u))];
+                if (NL >= 3) g = t3[(g << w3) | ((k >> (20 - w2 - w3)) & ((1u << w3) - 1u))];
+                const unsigned int idx = (g << wb) | ((k >> shift) & bmask);
+                if (ok && g != 0u) atomicAdd(&lds[(idx << clog) + cbase], 1u);
             }
-            if (ok && idx >= 0) atomicAdd(&lds[(idx << clog) + cbase], 1u);
         }
     }
 };
@@ -103,7 +96,8 @@ __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
     __shared__ unsigned int s_valid;
     const int tid = threadIdx.x, B = blockDim.x;
     const int nbins = 1 << a.width;
-    const int words = (a.slots * nbins) << a.copies_log2;
+    const int rows = NL == 0 ? 1 : a.slots + 1;   // after the first pass, row 0 is unused
+    const int words = (rows * nbins) << a.copies_log2;
     for (int i = tid; i < words; i += B) lds[i] = 0u;
     // The tables follow the histograms in LDS (all sizes are multiples of 4).
     unsigned int *tw = lds + words;
@@ -116,7 +110,7 @@ __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
 
     QuantStep<NL> st;
     st.lds = lds;
-    st.t1 = (const signed char *)tw;
+    st.t1 = (const unsigned char *)tw;
     st.t2 = st.t1 + 4096;
     st.t3 = st.t2 + a.t2_bytes;
     st.shift = a.shift;
@@ -131,10 +125,13 @@ __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
     // Every lane of a wavefront holds the same count (sums of ballots).
     if (NL == 0 && (tid & 63) == 0 && st.valid) atomicAdd(&s_valid, st.valid);
     __syncthreads();
+    // Flush the histograms (after the first pass, rows 1..: row 0 is
+    // never written).
     const int C = 1 << a.copies_log2;
+    const int first = NL == 0 ? 0 : nbins;
     for (int b = tid; b < a.slots * nbins; b += B) {
         unsigned int sum = 0;
-        for (int c = 0; c < C; ++c) sum += lds[(b << a.copies_log2) + c];
+        for (int c = 0; c < C; ++c) sum += lds[((b + first) << a.copies_log2) + c];
         if (sum) atomicAdd(&a.acc[b], (unsigned long long)sum);
     }
     if (NL == 0 && tid == 0 && s_valid) atomicAdd(a.n_valid, (unsigned long long)s_valid);
@@ -142,9 +139,9 @@ __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
 
 struct QuantWorkspace {
     unsigned long long *acc = nullptr;    // Q_ACC counters + 1 valid counter
-    signed char *tab = nullptr;           // the prefix tables
+    unsigned char *tab = nullptr;         // the prefix tables
     unsigned long long *h_acc = nullptr;  // pinned copy of the counters
-    signed char *h_tab = nullptr;         // pinned staging of the tables
+    unsigned char *h_tab = nullptr;       // pinned staging of the tables
 };
 
 std::mutex g_qmu;
@@ -178,9 +175,10 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, 
                int w2, int w3, int slots, int t2_bytes, int t3_bytes)
 {
     hipError_t e;
-    const size_t n = (size_t)slots << width;
+    const size_t n = (size_t)slots << width;          // counters read back
+    const size_t hist = (size_t)(nl == 0 ? 1 : slots + 1) << width; // LDS words per copy
     const size_t tab = nl == 0 ? 0 : 4096 + (nl >= 2 ? t2_bytes : 0) + (nl >= 3 ? t3_bytes : 0);
-    if (n > (size_t)Q_ACC || slots > Q_MAX_RANKS || tab > Q_TAB || n * 4 + tab > Q_LDS)
+    if (n > (size_t)Q_ACC || slots > Q_MAX_RANKS || tab > Q_TAB || hist * 4 + tab > Q_LDS)
         return fail(CUBE_EINVAL, "quantile pass too large");
     if ((e = hipMemsetAsync(w->acc, 0, (Q_ACC + 1) * 8, nullptr)) != hipSuccess)
         return hip_fail(e, "quantile counters");
@@ -189,8 +187,8 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, 
         return hip_fail(e, "quantile tables");
     // Up to eight copies of each histogram, as many as fit beside the tables.
     int clog = 0;
-    while (clog < 3 && (n << (clog + 1)) * 4 + tab <= Q_LDS) ++clog;
-    const size_t lds = (n << clog) * 4 + tab;
+    while (clog < 3 && (hist << (clog + 1)) * 4 + tab <= Q_LDS) ++clog;
+    const size_t lds = (hist << clog) * 4 + tab;
     QuantArgs a;
     memset(&a, 0, sizeof a);
     a.g = g;
@@ -323,32 +321,33 @@ int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t 
     for (int p = 0; p < npass; ++p) {
         const int nl = p + 1;  // prefix levels of this pass
         const int width = widths[p];
-        // Level tables: T1 maps the top 12 bits to the index among the
-        // 12-bit prefixes; T2 maps (that index, the next lev[1] bits) to the
-        // index among the longer prefixes; T3 likewise one level further.
-        signed char *t1 = w->h_tab;
-        memset(t1, -1, 4096);
+        // Level tables, entries index + 1 (0: none): T1 maps the top 12
+        // bits to the index among the 12-bit prefixes; T2 maps (that entry,
+        // the next lev[1] bits) to the index among the longer prefixes, with
+        // row 0 all zero; T3 likewise one level further.
+        unsigned char *t1 = w->h_tab;
+        memset(t1, 0, 4096);
         const std::vector<unsigned int> p1 = prefixes(want, 12);
-        for (size_t i = 0; i < p1.size(); ++i) t1[p1[i]] = (signed char)i;
+        for (size_t i = 0; i < p1.size(); ++i) t1[p1[i]] = (unsigned char)(i + 1);
         std::vector<unsigned int> deepest = p1;
         int t2_bytes = 0, t3_bytes = 0;
         if (nl >= 2) {
             const std::vector<unsigned int> p2 = prefixes(want, 12 + lev[1]);
-            signed char *t2 = t1 + 4096;
-            t2_bytes = (int)(p1.size() << lev[1]);
-            memset(t2, -1, (size_t)t2_bytes);
+            unsigned char *t2 = t1 + 4096;
+            t2_bytes = (int)((p1.size() + 1) << lev[1]);
+            memset(t2, 0, (size_t)t2_bytes);
             for (size_t i = 0; i < p2.size(); ++i) {
-                const unsigned int hi = (unsigned int)index_of(p1, p2[i] >> lev[1]);
-                t2[(hi << lev[1]) | (p2[i] & ((1u << lev[1]) - 1u))] = (signed char)i;
+                const unsigned int up = (unsigned int)index_of(p1, p2[i] >> lev[1]) + 1;
+                t2[(up << lev[1]) | (p2[i] & ((1u << lev[1]) - 1u))] = (unsigned char)(i + 1);
             }
             if (nl >= 3) {
                 const std::vector<unsigned int> p3 = prefixes(want, 12 + lev[1] + lev[2]);
-                signed char *t3 = t2 + t2_bytes;
-                t3_bytes = (int)(p2.size() << lev[2]);
-                memset(t3, -1, (size_t)t3_bytes);
+                unsigned char *t3 = t2 + t2_bytes;
+                t3_bytes = (int)((p2.size() + 1) << lev[2]);
+                memset(t3, 0, (size_t)t3_bytes);
                 for (size_t i = 0; i < p3.size(); ++i) {
-                    const unsigned int hi = (unsigned int)index_of(p2, p3[i] >> lev[2]);
-                    t3[(hi << lev[2]) | (p3[i] & ((1u << lev[2]) - 1u))] = (signed char)i;
+                    const unsigned int up = (unsigned int)index_of(p2, p3[i] >> lev[2]) + 1;
+                    t3[(up << lev[2]) | (p3[i] & ((1u << lev[2]) - 1u))] = (unsigned char)(i + 1);
                 }
                 deepest = p3;
             } else {
