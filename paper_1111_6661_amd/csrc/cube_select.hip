@@ -83,8 +83,11 @@ __device__ __forceinline__ void select_step(const float (&x)[NV], unsigned long 
         const bool match = ((k ^ c.prefix_hi) & c.hi_mask) == 0u;
         const unsigned long long inr = mv & __builtin_amdgcn_ballot_w64(match);
         const int b = (int)((k >> c.bin_shift) & c.bin_mask);
-        const int bb = keep_or_minus1(b, inr);
-        atomicAdd((unsigned int *)((char *)c.lds + ((bb << c.shift) + c.base)), 1u);
+        // Only lanes whose voxel is valid and under the prefix count: after
+        // the first pass most lanes do not, and sending them all to one
+        // dummy slot would serialize the atomic on a few LDS words.
+        if (v == v && match)
+            atomicAdd((unsigned int *)((char *)c.lds + ((b << c.shift) + c.base)), 1u);
         if (COLLECT && inr) {  // wavefront-uniform
             const int lane = threadIdx.x & 63;
             unsigned int base = 0;
