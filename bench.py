@@ -480,9 +480,9 @@ def main() -> int:
                     help="more offered loads (fractions of the plain capacity), e.g. 0.5,0.9")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (a cube would "
+              "shard by channel slabs with one all-gather of per-GPU records); "
+              "run with --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np
