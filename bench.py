@@ -11,18 +11,22 @@ The JSON line carries:
   value       voxels per second of the fused pass (inputs resident in HBM);
   roofline    the fused kernel's algorithmic bytes (4 per voxel) per launch
               divided by its average launch duration, measured with HIP events
-              on the launch stream, against the 8 TB/s HBM peak;
+              on the launch stream, against the 8 TB/s HBM peak, with the read
+              ceiling of the same access pattern (the read probe) beside it;
   cpu_baseline the oracle (single thread) on a bounded sample of the cube;
   p50_ms/p99_ms query latency of the continuous-batching server replaying a
               seeded Poisson query mix over 12 resident cubes (about 201 GiB);
-  extra       two-pass [min, max], stats-only and histogram-only timings; the
-              64-cube batch (graph replay vs plain launches); selection and
-              median; projection maps; out-of-core queries from host memory;
-              the 128 GiB precision-stress cube; the serving replay (plain vs
-              served); the launch shapes used; parity checks of each.
+  extra       the read probe; two-pass [min, max], stats-only and
+              histogram-only timings; the 64-cube batch (graph replay vs plain
+              launches, tile sizes including the automatic one); selection,
+              median and quantiles; projection maps; out-of-core queries from
+              host memory; the 128 GiB precision-stress cube; the serving
+              replay (plain vs served, and served with one fixed tile size);
+              the launch shapes used; parity checks of each.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        [--tune table|run|off] [--tune-save PATH] [--only-fused] [--no-...]
+       [--serve-seconds S] [--serve-sweep 0.5,0.9]
 """
 from __future__ import annotations
 
