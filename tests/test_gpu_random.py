@@ -77,14 +77,19 @@ def test_random_boxes(cs, box, nbins, frac):
 
 @settings(max_examples=15, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
-@given(box=boxes(), q=st.floats(0.0, 1.0))
-def test_random_select_and_project(cs, box, q):
+@given(box=boxes(), q=st.floats(0.0, 1.0),
+       levels=st.lists(st.floats(0.0, 1.0), min_size=1, max_size=64))
+def test_random_select_and_project(cs, box, q, levels):
     t, host = box
     ref = oracle.stats(host)
     if ref.n_valid:
         k = min(ref.n_valid - 1, int(q * ref.n_valid))
         assert same_f32(cs.select(t, k), oracle.select(host, k))
         assert cs.median(t)[0] == oracle.median(host)
+        got, nv = cs.quantiles(t, levels)
+        want = oracle.quantiles(host, levels)
+        assert nv == ref.n_valid
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (levels, got, want)
     mip, mom0, nv = (g.cpu().numpy() for g in cs.project(t))
     rmip, rmom0, rnv = oracle.project(host)
     assert np.array_equal(nv.view(np.uint32), rnv)
