@@ -1,8 +1,8 @@
 """Randomized GPU parity (hypothesis, derandomized so every run checks the
 same cases): random shapes, strided sub-boxes, offsets that break 16-byte
 alignment, NaN rates, value scales, ranges and bin counts.  Statistics,
-two-pass, fused and histogram-only against the oracle; selection and the
-projection maps too."""
+two-pass, fused and histogram-only against the oracle; selection,
+quantiles at random levels and the projection maps too."""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
