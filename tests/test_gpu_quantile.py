@@ -92,7 +92,8 @@ def test_many_ranks_in_few_buckets(cs):
     assert same(got, oracle.quantiles(a, levels))
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 2), (3, 1, 1), (7, 5, 301), (64, 64, 128)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 2), (3, 1, 1), (7, 5, 301), (64, 64, 128),
+                                   (1, 1, 3_000_001)])
 def test_shapes(cs, shape):
     rng = np.random.default_rng(sum(shape))
     a = (rng.standard_normal(shape) * 10).astype(np.float32)
