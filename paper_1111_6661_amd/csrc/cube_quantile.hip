@@ -31,6 +31,7 @@
 #include <mutex>
 #include <vector>
 
+#include "cube_quantile_plan.h"
 #include "cube_scan.h"
 
 namespace cube {
@@ -41,7 +42,7 @@ constexpr int Q_THREADS = 1024;
 constexpr int Q_MAX_RANKS = 2 * CUBE_MAX_QUANTILES;   // index + 1 fits a byte
 constexpr size_t Q_LDS = 160 * 1024 - 256;  // dynamic LDS of one block, static aside
 constexpr int Q_ACC = 32768;                // slots << bin width never exceeds this
-constexpr size_t Q_TAB = 4096 + 9 * 4096 + 129 * 64;  // bytes: T1, T2, T3 at most
+constexpr size_t Q_TAB = QP_TAB_MAX;        // bytes: T1, T2, T3 at most
 
 struct QuantArgs {
     Geom g;
@@ -224,163 +225,42 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, 
     return CUBE_OK;
 }
 
-// A rank being refined: the key bits found so far (at the top of `key`) and
-// the rank left inside that prefix.
-struct Want {
-    unsigned long long rank;
-    unsigned int key;
+// The passes on the GPU for the host-side plan (cube_quantile_plan.h).
+struct GpuPasses {
+    QuantWorkspace *w;
+    Geom g;
+    int blocks;
+    int first(const unsigned long long **counts, unsigned long long *n)
+    {
+        const int rc = quant_pass(w, g, blocks, 0, 20, 12, 0, 0, 1, 0, 0);
+        if (rc) return rc;
+        *counts = w->h_acc;
+        *n = w->h_acc[Q_ACC];
+        return CUBE_OK;
+    }
+    // The tables are already staged in w->h_tab, which quant_pass uploads.
+    int refine(const QuantPassSpec &s, const unsigned char *, const unsigned long long **counts)
+    {
+        const int rc = quant_pass(w, g, blocks, s.nl, s.shift, s.width, s.w2, s.w3, s.slots,
+                                  s.t2_bytes, s.t3_bytes);
+        if (rc) return rc;
+        *counts = w->h_acc;
+        return CUBE_OK;
+    }
 };
-
-// The bin of `h` (nbins counters) holding rank r; r becomes the rank
-// inside that bin.  The counts sum to more than r by construction.
-unsigned int pick_bin(const unsigned long long *h, int nbins, unsigned long long &r)
-{
-    int b = 0;
-    while (b < nbins - 1 && h[b] <= r) r -= h[b++];
-    return (unsigned int)b;
-}
-
-float key_to_float(unsigned int k)
-{
-    const unsigned int u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
-    float f;
-    memcpy(&f, &u, 4);
-    return f;
-}
-
-double interpolate(double a, double b, double f)
-{
-    if (a == b) return a;
-    if (isinf(a) && isinf(b)) return NAN;
-    if (isinf(a)) return a;
-    if (isinf(b)) return b;
-    return a + f * (b - a);
-}
-
-// The distinct values of the top `bits` key bits among the wanted ranks,
-// ascending.
-std::vector<unsigned int> prefixes(const std::vector<Want> &want, int bits)
-{
-    std::vector<unsigned int> p;
-    for (const Want &x : want) p.push_back(x.key >> (32 - bits));
-    std::sort(p.begin(), p.end());
-    p.erase(std::unique(p.begin(), p.end()), p.end());
-    return p;
-}
-
-size_t index_of(const std::vector<unsigned int> &p, unsigned int v)
-{
-    return std::lower_bound(p.begin(), p.end(), v) - p.begin();
-}
-
-size_t index_of_rank(const std::vector<unsigned long long> &r, unsigned long long v)
-{
-    return std::lower_bound(r.begin(), r.end(), v) - r.begin();
-}
 
 int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t *n_valid_out)
 {
     QuantWorkspace *w = nullptr;
     int rc = quant_ws(&w);
     if (rc) return rc;
-    const int blocks = cu_count() * 2;
-    Geom g;
-    scan_geom(box, blocks, &g);
-
-    // The top 12 bits, and the valid count.
-    if ((rc = quant_pass(w, g, blocks, 0, 20, 12, 0, 0, 1, 0, 0))) return rc;
-    const unsigned long long n = w->h_acc[Q_ACC];
-    if (n_valid_out) *n_valid_out = n;
-    if (n == 0) return fail(CUBE_EINVAL, "no valid voxel");
-
-    // The ranks the levels need, ascending and distinct (at most 2m).
-    std::vector<unsigned long long> ranks;
-    for (int i = 0; i < m; ++i) {
-        const double h = q[i] * (double)(n - 1);
-        const double j = floor(h);
-        ranks.push_back((unsigned long long)j);
-        if (h - j > 0.0) ranks.push_back((unsigned long long)j + 1);
-    }
-    std::sort(ranks.begin(), ranks.end());
-    ranks.erase(std::unique(ranks.begin(), ranks.end()), ranks.end());
-    std::vector<Want> want(ranks.size());
-    for (size_t i = 0; i < ranks.size(); ++i) {
-        want[i].rank = ranks[i];
-        want[i].key = pick_bin(w->h_acc, 4096, want[i].rank) << 20;
-    }
-
-    // The remaining 20 bits: 12 + 8 when the ranks lie in at most 8 top
-    // buckets and number at most 96 (the tables and histograms of both
-    // passes fit in LDS), else 8 + 6 + 6.
-    const bool wide = prefixes(want, 12).size() <= 8 && want.size() <= 96;
-    static const int wide_w[] = {12, 8}, narrow_w[] = {8, 6, 6};
-    const int *widths = wide ? wide_w : narrow_w;
-    const int npass = wide ? 2 : 3;
-    int lev[3] = {12, 0, 0};  // widths of the prefix levels
-    int done = 12;            // key bits found so far
-    for (int p = 0; p < npass; ++p) {
-        const int nl = p + 1;  // prefix levels of this pass
-        const int width = widths[p];
-        // Level tables, entries index + 1 (0: none): T1 maps the top 12
-        // bits to the index among the 12-bit prefixes; T2 maps (that entry,
-        // the next lev[1] bits) to the index among the longer prefixes, with
-        // row 0 all zero; T3 likewise one level further.
-        unsigned char *t1 = w->h_tab;
-        memset(t1, 0, 4096);
-        const std::vector<unsigned int> p1 = prefixes(want, 12);
-        for (size_t i = 0; i < p1.size(); ++i) t1[p1[i]] = (unsigned char)(i + 1);
-        std::vector<unsigned int> deepest = p1;
-        int t2_bytes = 0, t3_bytes = 0;
-        if (nl >= 2) {
-            const std::vector<unsigned int> p2 = prefixes(want, 12 + lev[1]);
-            unsigned char *t2 = t1 + 4096;
-            t2_bytes = (int)((p1.size() + 1) << lev[1]);
-            memset(t2, 0, (size_t)t2_bytes);
-            for (size_t i = 0; i < p2.size(); ++i) {
-                const unsigned int up = (unsigned int)index_of(p1, p2[i] >> lev[1]) + 1;
-                t2[(up << lev[1]) | (p2[i] & ((1u << lev[1]) - 1u))] = (unsigned char)(i + 1);
-            }
-            if (nl >= 3) {
-                const std::vector<unsigned int> p3 = prefixes(want, 12 + lev[1] + lev[2]);
-                unsigned char *t3 = t2 + t2_bytes;
-                t3_bytes = (int)((p2.size() + 1) << lev[2]);
-                memset(t3, 0, (size_t)t3_bytes);
-                for (size_t i = 0; i < p3.size(); ++i) {
-                    const unsigned int up = (unsigned int)index_of(p2, p3[i] >> lev[2]) + 1;
-                    t3[(up << lev[2]) | (p3[i] & ((1u << lev[2]) - 1u))] = (unsigned char)(i + 1);
-                }
-                deepest = p3;
-            } else {
-                deepest = p2;
-            }
-        }
-        const int shift = 32 - done - width;
-        if ((rc = quant_pass(w, g, blocks, nl, shift, width, lev[1], lev[2], (int)deepest.size(),
-                             t2_bytes, t3_bytes)))
-            return rc;
-        for (Want &x : want) {
-            const size_t slot = index_of(deepest, x.key >> (32 - done));
-            const unsigned int b =
-                pick_bin(w->h_acc + (slot << width), 1 << width, x.rank);
-            x.key |= b << shift;
-        }
-        if (nl < 3) lev[nl] = width;
-        done += width;
-    }
-
-    // The levels: the voxels of ranks j and j + 1, interpolated.
-    auto value_of = [&](unsigned long long r) {
-        return (double)key_to_float(want[index_of_rank(ranks, r)].key);
-    };
-    for (int i = 0; i < m; ++i) {
-        const double h = q[i] * (double)(n - 1);
-        const double j = floor(h);
-        const double f = h - j;
-        const double a = value_of((unsigned long long)j);
-        const double b = f > 0.0 ? value_of((unsigned long long)j + 1) : a;
-        out[i] = interpolate(a, b, f);
-    }
-    return CUBE_OK;
+    GpuPasses P;
+    P.w = w;
+    P.blocks = cu_count() * 2;
+    scan_geom(box, P.blocks, &P.g);
+    rc = quantiles_run(P, q, m, out, n_valid_out, w->h_tab, 1);
+    if (rc == 1) return fail(CUBE_EINVAL, "no valid voxel");
+    return rc;
 }
 
 }  // namespace
