@@ -1,8 +1,9 @@
 """Full-size parity (GPU, slow): the 16 GiB brick against the oracle over the
-whole cube, in the launch configuration the benchmark times; and the
+whole cube, in the launch configuration the benchmark times; the
 precision-stress recipe (offset 1e4, noise 1e-3, sources up to 1e3) at 16 GiB,
 where the FP32-only accumulation modes are reported beside the production
-FP64-merge path.
+FP64-merge path; and the full 128 GiB stress cube, by properties, sampled
+sub-boxes and ranks.
 
 The oracle runs single-threaded on host copies; these tests take a minute or
 two each and are marked `slow` as well as `gpu`.
@@ -136,3 +137,71 @@ def test_precision_stress_16g(cs):
             json.dump({"recipe": "stress128g scaled to 2048x2048x1024", "oracle_std": ref.std,
                        "oracle_mean": ref.mean,
                        "rel_err_mean_std": {k: list(v) for k, v in errs.items()}}, f, indent=1)
+
+
+@pytest.mark.timeout(900)
+def test_stress128g_full_size(cs):
+    """The 128 GiB stress cube (2^35 voxels) in the launch configuration the
+    benchmark times: properties that hold at any size on the whole cube,
+    sub-boxes at the start, the middle and the far end (element offsets past
+    2^34) against the oracle, and selection, median and quantiles checked by
+    their ranks (counted on the GPU, a chunk of planes at a time)."""
+    import synth
+    r = synth.WORKLOADS["stress128g"]
+    nb = synth.HIST_BINS["stress128g"]
+    t = synth.cube_tensor(r, synth.BASE_SEED + 4, device="cuda")
+    nz = t.shape[0]
+    st = cs.stats(t)
+    assert st.n_total == r.n and st.n_valid + st.n_nan == r.n
+    st_f, c_f = cs.stats_hist(t, st.min, st.max, nb)
+    st_2, c_2 = cs.stats_hist_minmax(t, nb)
+    assert np.array_equal(c_f, c_2)
+    assert int(c_f.sum()) == r.n and int(c_f[nb]) == 0 and int(c_f[nb + 1]) == 0
+    assert int(c_f[nb + 2]) == st.n_nan
+    for s in (st_f, st_2):
+        assert s.min == st.min and s.max == st.max and s.n_valid == st.n_valid
+        assert abs(s.mean - st.mean) <= 1e-9 * abs(st.mean) and abs(s.std - st.std) <= 1e-6 * st.std
+
+    # sub-boxes against the oracle, including the far end of the cube
+    for sl in (np.s_[0:2], np.s_[nz // 2:nz // 2 + 2, 100:3000, 7:4001], np.s_[nz - 2:nz]):
+        sub = t[sl]
+        host = sub.cpu().numpy()
+        ref = oracle.stats(host)
+        assert_stats_match(cs.stats(sub), ref, f"stats {sl}")
+        if ref.n_valid:
+            s2, c2 = cs.stats_hist_minmax(sub, nb)
+            assert_stats_match(s2, ref, f"two-pass {sl}")
+            assert_counts_match(c2, oracle.hist(host, ref.min, ref.max, nb), f"counts {sl}")
+        del sub, host
+
+    def count_below(v, inclusive):
+        n = 0
+        for z0 in range(0, nz, 128):
+            blk = t[z0:z0 + 128]
+            n += int(((blk <= v) if inclusive else (blk < v)).sum())
+        return n
+
+    def rank_holds(v, k):
+        return count_below(v, False) <= k < count_below(v, True)
+
+    n = int(st.n_valid)
+    k_mid = (n - 1) // 2
+    v = cs.select(t, k_mid)
+    assert rank_holds(v, k_mid)
+    med, med_n = cs.median(t)
+    assert med_n == n
+    if n % 2 == 0:
+        nxt = cs.select(t, k_mid + 1)
+        assert med == (float(v) + float(nxt)) / 2.0
+    else:
+        assert med == v
+    qv, qn = cs.quantiles(t, [0.0, 0.25, 0.75, 1.0])
+    assert qn == n and qv[0] == st.min and qv[3] == st.max
+    for lvl, got in ((0.25, qv[1]), (0.75, qv[2])):
+        h = lvl * (n - 1)
+        j = int(np.floor(h))
+        a, b = cs.select(t, j), cs.select(t, j + 1)
+        assert got == oracle.quantiles(np.array([a, b], np.float32), [h - j])[0]
+        assert rank_holds(a, j) and rank_holds(b, j + 1)
+    del t
+    torch.cuda.empty_cache()
