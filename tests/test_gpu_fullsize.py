@@ -2,8 +2,8 @@
 whole cube, in the launch configuration the benchmark times; the
 precision-stress recipe (offset 1e4, noise 1e-3, sources up to 1e3) at 16 GiB,
 where the FP32-only accumulation modes are reported beside the production
-FP64-merge path; and the full 128 GiB stress cube, by properties, sampled
-sub-boxes and ranks.
+FP64-merge path; the full 128 GiB stress cube, by properties, sampled
+sub-boxes and ranks; and the serving set at its real size (about 201 GiB).
 
 The oracle runs single-threaded on host copies; these tests take a minute or
 two each and are marked `slow` as well as `gpu`.
@@ -205,3 +205,94 @@ def test_stress128g_full_size(cs):
         assert rank_holds(a, j) and rank_holds(b, j + 1)
     del t
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_serving_full_size(cs):
+    """The serving workload at its real size: twelve resident cubes (about
+    201 GiB, the largest 2^34 voxels) and the seeded query mix, plus
+    minmax-histogram queries.  Every served result equals the single-box
+    calls bit for bit (same tiling-independent counts and extrema, same
+    statistics bytes when the single-box pass is run as a one-query batch);
+    a few small sub-boxes are checked against the oracle."""
+    import threading
+
+    import synth
+    from paper_1111_6661_amd import workloads
+    recipes = synth.serve_recipes()
+    cubes = [synth.cube_tensor(r, synth.BASE_SEED + 3 + i, device="cuda")
+             for i, r in enumerate(recipes)]
+    try:
+        ranges = []
+        for c in cubes:
+            s = cs.stats(c)
+            ranges.append(((s.min, s.max), (s.mean - 2 * s.std, s.mean + 2 * s.std)))
+        shapes = [tuple(c.shape) for c in cubes]
+        specs = workloads.query_stream(shapes, ranges, 80, 1e9, synth.BASE_SEED + 40,
+                                       cs.CUBE_Q_STATS, cs.CUBE_Q_FUSED)
+        n = len(specs)
+        out = torch.zeros((n, 64), dtype=torch.uint8, device="cuda")
+        cnt = torch.zeros((n, 4096 + 3), dtype=torch.int64, device="cuda")
+        qs, views = [], []
+        for i, q in enumerate(specs):
+            z0, z1, y0, y1, x0, x1 = q.box
+            v = cubes[q.cube][z0:z1, y0:y1, x0:x1]
+            kind = q.kind if i % 5 else cs.CUBE_Q_MINMAX
+            nb = q.nbins or 256
+            p, d = cs.box_of(v)
+            qs.append(cs.make_query(p, d, kind, nb, q.lo, q.hi, out[i].data_ptr(),
+                                    cnt[i].data_ptr()))
+            views.append((v, kind, nb, q.lo, q.hi))
+        srv = cs.Server(cs.CUBE_SERVE_BATCHED, slots=4, max_batch=32)
+        ids = [0] * n
+
+        def submit():
+            for i, q in enumerate(qs):
+                ids[i] = srv.submit(q)
+
+        th = threading.Thread(target=submit)
+        th.start()
+        th.join()
+        for i in ids:
+            assert srv.wait(i, timeout_s=120) >= 0
+        srv.close()
+        torch.cuda.synchronize()
+        for i, (v, kind, nb, lo, hi) in enumerate(views):
+            # the same query alone, through a one-query batch with the
+            # server's automatic tile: identical bytes
+            o1 = torch.zeros(64, dtype=torch.uint8, device="cuda")
+            c1 = torch.zeros(nb + 3, dtype=torch.int64, device="cuda")
+            p, d = cs.box_of(v)
+            b = cs.Batch(tile_voxels=0)
+            b.enqueue([cs.make_query(p, d, kind, nb, lo, hi, o1.data_ptr(), c1.data_ptr())])
+            b.check()
+            b.close()
+            assert torch.equal(o1, out[i]), f"query {i} stats differ from the query alone"
+            if kind != cs.CUBE_Q_STATS:
+                assert torch.equal(c1, cnt[i, :nb + 3]), f"query {i} counts differ"
+            # and the plain single-box calls: exact counts and extrema
+            st = cs.Stats.from_bytes(out[i].cpu().numpy().tobytes())
+            ref = cs.stats(v)
+            assert st.n_valid == ref.n_valid and st.n_nan == ref.n_nan
+            assert same_bits(st.min, ref.min) and same_bits(st.max, ref.max)
+            if kind == cs.CUBE_Q_FUSED:
+                _, cf = cs.stats_hist(v, lo, hi, nb)
+                assert np.array_equal(cnt[i, :nb + 3].cpu().numpy().view(np.uint64), cf)
+            elif kind == cs.CUBE_Q_MINMAX:
+                _, cm = cs.stats_hist_minmax(v, nb)
+                assert np.array_equal(cnt[i, :nb + 3].cpu().numpy().view(np.uint64), cm)
+        # small sub-boxes against the oracle
+        small = sorted(range(n), key=lambda i: specs[i].voxels)[:3]
+        for i in small:
+            v, kind, nb, lo, hi = views[i]
+            host = v.cpu().numpy()
+            ref = oracle.stats(host)
+            assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref,
+                               f"served query {i}")
+    finally:
+        del cubes
+        torch.cuda.empty_cache()
+
+
+def same_bits(a, b):
+    return np.float32(a).view(np.uint32) == np.float32(b).view(np.uint32)
