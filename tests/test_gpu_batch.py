@@ -145,15 +145,28 @@ def test_automatic_tile_sizes(cs):
 
 
 def test_batch_of_workload_items(cs):
-    """The 64-item workload shape (uneven sizes), two-pass 512 bins each."""
+    """The whole 64-item workload (uneven sizes, 1.6e8 voxels), two-pass 512
+    bins each, in the form the benchmark times (a graph replay with the
+    automatic tile size), every item against the oracle."""
     import synth
-    recs = synth.batch_item_recipes()[:16]
-    items = [synth.cube_tensor(r, 77 + i, device="cuda") for i, r in enumerate(recs)]
+    recs = synth.batch_item_recipes()
+    items = [synth.cube_tensor(r, synth.BASE_SEED + 2 + i, device="cuda")
+             for i, r in enumerate(recs)]
     outs = Outputs(len(items), 512)
     qs = queries_for(cs, items, outs, [cs.CUBE_Q_MINMAX], [512])
-    cs.cube_batch_run(qs)
+    b = cs.Batch(tile_voxels=0)
+    b.enqueue(qs)
+    b.check()
+    first_out, first_cnt = outs.out.clone(), outs.cnt.clone()
+    b.graph_launch()
+    b.graph_launch()
+    b.check()
+    b.close()
+    assert torch.equal(outs.out, first_out) and torch.equal(outs.cnt, first_cnt)
     for i, t in enumerate(items):
         check_query(cs, outs, i, t, cs.CUBE_Q_MINMAX, 512)
+    del items
+    torch.cuda.empty_cache()
 
 
 def test_batch_validation(cs):
