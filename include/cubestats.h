@@ -349,9 +349,11 @@ CUBE_API int cube_batch_run(const cube_query_t *q, int32_t n);
 /*
  * Out-of-core query over a cube in HOST memory.  The paper's cubes exceed
  * one device and are processed as sub-cubes while loading overlaps
- * processing (Sections 2 and 3).  `q->ptr` is host memory (pinned memory
- * from hipHostMalloc streams at the full link rate; pageable memory is
- * accepted and staged by the runtime); `q->out` (cube_stats_t) and
+ * processing (Sections 2 and 3).  `q->ptr` is host memory: pinned memory
+ * (hipHostMalloc) is copied by the DMA engine directly; pageable memory is
+ * gathered by a few host threads into three pinned 64 MiB staging buffers
+ * (kept until cube_shutdown) while the previous chunk is copied, in chunks
+ * of at most 2^24 voxels.  `q->out` (cube_stats_t) and
  * `q->counts` (nbins + 3 uint64) are HOST outputs; `q->kind`, `dims`, `lo`,
  * `hi` and `nbins` mean what they mean for the resident calls.  The box is
  * cut into chunks of at most `chunk_voxels` voxels (0 = 2^28; allowed

@@ -14,9 +14,17 @@
 // A chunk is a run of whole rows of one plane (or a piece of one row when a
 // row alone exceeds the chunk), so a strided host box is gathered by one 2-D
 // copy per chunk into a dense device buffer.
+//
+// Pinned host memory is copied by the DMA engine directly.  Pageable memory
+// would go through the HIP runtime's own staging, one host thread at a time;
+// here a few host threads gather each chunk (at most 64 MiB) into one of
+// three pinned staging buffers while the DMA engine moves the previous one,
+// and a staging buffer is reused only once the copy that read it is done.
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "cube_device.h"
@@ -28,6 +36,8 @@ namespace {
 constexpr int NBUF = 3;
 constexpr int64_t DEFAULT_CHUNK = (int64_t)1 << 28;  // voxels (1 GiB)
 constexpr int64_t MIN_CHUNK = (int64_t)1 << 12;
+constexpr int NSTAGE = 3;
+constexpr int64_t STAGE_CHUNK = (int64_t)1 << 24;    // voxels (64 MiB) per staged chunk
 
 // Merge per-chunk results in chunk order (one thread; the chunk count is
 // small).  Writes the result and, when range_out is given, the [min, max]
@@ -95,6 +105,9 @@ struct HostWorkspace {
     cube_stats_t *d_out = nullptr, *h_out = nullptr;
     unsigned long long *d_counts = nullptr, *h_counts = nullptr;
     HistRange *d_range = nullptr;
+    // pinned staging of pageable sources
+    float *stage[NSTAGE] = {};
+    hipEvent_t stage_free[NSTAGE] = {};
 };
 
 HostWorkspace g_hws[64];
@@ -111,6 +124,9 @@ int hws_init(HostWorkspace &w)
         if ((e = hipEventCreateWithFlags(&w.copied[i], hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&w.freed[i], hipEventDisableTiming)) != hipSuccess)
             return hip_fail(e, "streaming events");
+    for (int i = 0; i < NSTAGE; ++i)
+        if ((e = hipEventCreateWithFlags(&w.stage_free[i], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "staging events");
     if ((e = hipMalloc(&w.d_out, sizeof(cube_stats_t))) != hipSuccess ||
         (e = hipMalloc(&w.d_counts, ((size_t)CUBE_MAX_BINS + 3) * 8)) != hipSuccess ||
         (e = hipMalloc(&w.d_range, sizeof(HistRange))) != hipSuccess ||
@@ -164,14 +180,51 @@ void plan_chunks(const Geom &g, int64_t cv, std::vector<Chunk> &out)
     }
 }
 
+// Gather rows [0, rows) of len floats at pitch sy from src into dense dst
+// with up to `threads` host threads, each taking an equal share of the
+// voxels.
+void gather_rows(float *dst, const float *src, int64_t sy, int64_t rows, int64_t len,
+                 int threads)
+{
+    const int64_t total = rows * len;
+    auto part = [&](int t) {
+        int64_t i = total * t / threads;
+        const int64_t end = total * (t + 1) / threads;
+        while (i < end) {
+            const int64_t r = i / len, c = i - r * len;
+            const int64_t n = std::min(len - c, end - i);
+            memcpy(dst + i, src + r * sy + c, (size_t)n * 4);
+            i += n;
+        }
+    };
+    if (threads <= 1 || total < ((int64_t)1 << 18)) {
+        threads = 1;
+        part(0);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(part, t);
+    part(0);
+    for (std::thread &th : pool) th.join();
+}
+
+int gather_threads()
+{
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(8u, hc / 2));
+}
+
 // One streaming pass over every chunk.  stats: per-chunk records into
 // w.d_chunks; hist: counts added into w.d_counts over `range` or, when
-// dev_range is set, the range on the device.
+// dev_range is set, the range on the device.  staged: the source is pageable
+// and goes through the pinned staging buffers.
 int stream_pass(HostWorkspace &w, const Geom &g, const std::vector<Chunk> &chunks, bool stats,
-                bool hist, int nbins, const HistRange &range, const HistRange *dev_range)
+                bool hist, int nbins, const HistRange &range, const HistRange *dev_range,
+                bool staged)
 {
     hipError_t e;
     int rc;
+    const int threads = staged ? gather_threads() : 1;
     for (size_t i = 0; i < chunks.size(); ++i) {
         const Chunk &c = chunks[i];
         const int k = (int)(i % NBUF);
@@ -179,12 +232,23 @@ int stream_pass(HostWorkspace &w, const Geom &g, const std::vector<Chunk> &chunk
         // The buffer is free once the pass that last read it has run.
         if ((e = hipStreamWaitEvent(w.copy, w.freed[k], 0)) != hipSuccess)
             return hip_fail(e, "wait for buffer");
-        if (c.rows == 1)
+        if (staged) {
+            // The staging buffer is free once the copy that last read it is
+            // done; then the host gathers the chunk into it.
+            const int s = (int)(i % NSTAGE);
+            if ((e = hipEventSynchronize(w.stage_free[s])) != hipSuccess)
+                return hip_fail(e, "wait for staging");
+            gather_rows(w.stage[s], src, g.sy, c.rows, c.len, threads);
+            e = hipMemcpyAsync(w.buf[k], w.stage[s], (size_t)(c.len * c.rows) * 4,
+                               hipMemcpyHostToDevice, w.copy);
+            if (e == hipSuccess) e = hipEventRecord(w.stage_free[s], w.copy);
+        } else if (c.rows == 1) {
             e = hipMemcpyAsync(w.buf[k], src, (size_t)c.len * 4, hipMemcpyHostToDevice, w.copy);
-        else
+        } else {
             e = hipMemcpy2DAsync(w.buf[k], (size_t)c.len * 4, src, (size_t)g.sy * 4,
                                  (size_t)c.len * 4, (size_t)c.rows, hipMemcpyHostToDevice,
                                  w.copy);
+        }
         if (e != hipSuccess) return hip_fail(e, "chunk copy");
         if ((e = hipEventRecord(w.copied[k], w.copy)) != hipSuccess)
             return hip_fail(e, "copy event");
@@ -239,10 +303,14 @@ int host_query(const cube_query_t *q, int64_t chunk_voxels)
     // The input must be host memory: device memory takes the resident path.
     hipPointerAttribute_t attr;
     memset(&attr, 0, sizeof attr);
-    if (hipPointerGetAttributes(&attr, q->ptr) == hipSuccess &&
-        attr.type == hipMemoryTypeDevice)
+    const bool known = hipPointerGetAttributes(&attr, q->ptr) == hipSuccess;
+    if (known && attr.type == hipMemoryTypeDevice)
         return fail(CUBE_EINVAL, "the box is in device memory: use the resident entry points");
     (void)hipGetLastError();  // a pageable pointer leaves an error code behind
+    // Pinned (registered) host memory is copied directly; anything else is
+    // staged.
+    const bool staged = !(known && attr.type == hipMemoryTypeHost);
+    if (staged) chunk_voxels = std::min(chunk_voxels, STAGE_CHUNK);
     int dev = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "device");
@@ -260,9 +328,16 @@ int host_query(const cube_query_t *q, int64_t chunk_voxels)
     if ((rc = hws_reserve(w, std::min<int64_t>(chunk_voxels, (int64_t)box.n + 4),
                           chunks.size())))
         return rc;
+    if (staged && box.n && !w.stage[0])
+        for (int i = 0; i < NSTAGE; ++i)
+            if ((e = hipHostMalloc(&w.stage[i], (size_t)STAGE_CHUNK * 4)) != hipSuccess)
+                return hip_fail(e, "staging buffers");
     // Every buffer starts free.
     for (int k = 0; k < NBUF; ++k)
         if ((e = hipEventRecord(w.freed[k], w.compute)) != hipSuccess)
+            return hip_fail(e, "initial events");
+    for (int i = 0; i < NSTAGE; ++i)
+        if ((e = hipEventRecord(w.stage_free[i], w.copy)) != hipSuccess)
             return hip_fail(e, "initial events");
     if (box.n == 0) {
         if ((rc = write_empty(w.d_out, w.d_counts, nbins, w.compute))) return rc;
@@ -274,7 +349,7 @@ int host_query(const cube_query_t *q, int64_t chunk_voxels)
         }
         const bool fused_pass = kind != CUBE_Q_MINMAX;
         if ((rc = stream_pass(w, g, chunks, want_stats, want_hist && fused_pass, nbins, range,
-                              nullptr)))
+                              nullptr, staged)))
             return rc;
         if (want_stats) {
             hipLaunchKernelGGL(k_merge_chunks, dim3(1), dim3(64), 0, w.compute, w.d_chunks,
@@ -283,7 +358,7 @@ int host_query(const cube_query_t *q, int64_t chunk_voxels)
             if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "chunk merge");
         }
         if (kind == CUBE_Q_MINMAX &&
-            (rc = stream_pass(w, g, chunks, false, true, nbins, range, w.d_range)))
+            (rc = stream_pass(w, g, chunks, false, true, nbins, range, w.d_range, staged)))
             return rc;
     }
     if (want_stats &&
@@ -317,6 +392,11 @@ void host_release()
             w.buf[i] = nullptr;
             hipEventDestroy(w.copied[i]);
             hipEventDestroy(w.freed[i]);
+        }
+        for (int i = 0; i < NSTAGE; ++i) {
+            hipHostFree(w.stage[i]);
+            w.stage[i] = nullptr;
+            hipEventDestroy(w.stage_free[i]);
         }
         w.buf_voxels = 0;
         hipFree(w.d_chunks);

@@ -91,3 +91,24 @@ def test_host_special_cases(cs):
         cs.host_query(nan, cs.CUBE_Q_STATS, chunk_voxels=100)
     with pytest.raises(cs.CubeError):
         cs.host_query(a, cs.CUBE_Q_HIST, 64, 1.0, 0.0)
+
+
+def test_host_pageable_staging_large(cs):
+    """Pageable sources go through pinned staging buffers, gathered by several
+    host threads: a strided view whose planes (about 10^6 voxels, rows at a
+    pitch) fill a chunk each, and one row longer than a staged chunk (2^24
+    voxels), with default chunk sizes; the same arrays pinned give the same
+    counts and extrema."""
+    rng = np.random.default_rng(77)
+    full = (rng.standard_normal((8, 1024, 1024)) * 4 + 1).astype(np.float32)
+    full[rng.random(full.shape) < 0.01] = np.nan
+    view = full[1:8, 5:1000, 3:1020]
+    check_kinds(cs, view, 0, nbins=300, lo=-10.0, hi=12.0, what="large strided view")
+    row = (rng.standard_normal((1 << 24) + 12345) * 2).astype(np.float32)
+    row[::977] = np.nan
+    check_kinds(cs, row, 0, nbins=64, lo=-6.0, hi=6.0, what="row over two staged chunks")
+    pinned = torch.from_numpy(row).pin_memory()
+    st_p, cnt_p = cs.host_query(pinned, cs.CUBE_Q_FUSED, 64, -6.0, 6.0)
+    st_s, cnt_s = cs.host_query(row, cs.CUBE_Q_FUSED, 64, -6.0, 6.0)
+    assert np.array_equal(cnt_p, cnt_s)
+    assert st_p.min == st_s.min and st_p.max == st_s.max and st_p.n_valid == st_s.n_valid
