@@ -202,8 +202,15 @@ void gather_rows(float *dst, const float *src, int64_t sy, int64_t rows, int64_t
         part(0);
         return;
     }
+    // A part whose thread cannot be started runs here instead (no exception
+    // leaves the library).
     std::vector<std::thread> pool;
-    for (int t = 1; t < threads; ++t) pool.emplace_back(part, t);
+    int started = 1;
+    try {
+        for (int t = 1; t < threads; ++t, ++started) pool.emplace_back(part, t);
+    } catch (...) {
+    }
+    for (int t = started; t < threads; ++t) part(t);
     part(0);
     for (std::thread &th : pool) th.join();
 }
