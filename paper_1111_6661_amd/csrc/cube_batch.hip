@@ -394,11 +394,13 @@ extern "C" {
 
 int cube_batch_create(cube_batch_t **out)
 {
+    CUBE_GUARD_BEGIN
     if (!out) return fail(CUBE_EINVAL, "out is NULL");
     cube_batch *b = new cube_batch;
     hipGetDevice(&b->device);
     *out = b;
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 void cube_batch_destroy(cube_batch_t *b)
@@ -430,6 +432,7 @@ int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads)
 
 int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *stream)
 {
+    CUBE_GUARD_BEGIN
     if (!b) return fail(CUBE_EINVAL, "batch is NULL");
     if (n < 0 || (n > 0 && !q)) return fail(CUBE_EINVAL, "bad query list");
     std::lock_guard<std::mutex> lk(b->mu);
@@ -578,6 +581,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     b->have_work = n > 0;
     if (!b->have_work) return CUBE_OK;
     return launch_batch(b, s);
+    CUBE_GUARD_END
 }
 
 int cube_batch_set_order(cube_batch_t *b, int32_t order)
@@ -598,14 +602,17 @@ int cube_batch_query_done(cube_batch_t *b, int32_t i)
 
 int cube_batch_relaunch(cube_batch_t *b, void *stream)
 {
+    CUBE_GUARD_BEGIN
     if (!b) return fail(CUBE_EINVAL, "batch is NULL");
     std::lock_guard<std::mutex> lk(b->mu);
     if (!b->have_work) return CUBE_OK;
     return launch_batch(b, (hipStream_t)stream);
+    CUBE_GUARD_END
 }
 
 int cube_batch_graph_launch(cube_batch_t *b, void *stream)
 {
+    CUBE_GUARD_BEGIN
     if (!b) return fail(CUBE_EINVAL, "batch is NULL");
     std::lock_guard<std::mutex> lk(b->mu);
     if (!b->have_work) return CUBE_OK;
@@ -644,6 +651,7 @@ int cube_batch_graph_launch(cube_batch_t *b, void *stream)
     if ((e = hipGraphLaunch(b->graph_exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
     if ((e = mark_launched(b, s)) != hipSuccess) return hip_fail(e, "batch event");
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 int cube_batch_check(cube_batch_t *b)
@@ -664,6 +672,7 @@ int cube_batch_check(cube_batch_t *b)
 
 int cube_batch_run(const cube_query_t *q, int32_t n)
 {
+    CUBE_GUARD_BEGIN
     cube_batch_t *b = nullptr;
     int rc = cube_batch_create(&b);
     if (rc) return rc;
@@ -671,6 +680,7 @@ int cube_batch_run(const cube_query_t *q, int32_t n)
     if (!rc) rc = cube_batch_check(b);
     cube_batch_destroy(b);
     return rc;
+    CUBE_GUARD_END
 }
 
 }  // extern "C"

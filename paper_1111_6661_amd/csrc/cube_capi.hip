@@ -547,59 +547,75 @@ const char *cube_last_error(void) { return g_err.c_str(); }
 int cube_stats(const float *ptr, int64_t nx, int64_t ny, int64_t nz, const int64_t *stride,
                cube_stats_t *out)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     const int64_t dims[5] = {nx, ny, nz, stride ? stride[0] : 0, stride ? stride[1] : 0};
     return run_sync(OP_STATS, ptr, dims, 0.f, 0.f, 1, out, nullptr);
+    CUBE_GUARD_END
 }
 
 int cube_hist(const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
               uint64_t *counts)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     return run_sync(OP_HIST, ptr, dims, lo, hi, nbins, nullptr, counts);
+    CUBE_GUARD_END
 }
 
 int cube_stats_hist(const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
                     cube_stats_t *out, uint64_t *counts)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     return run_sync(OP_FUSED, ptr, dims, lo, hi, nbins, out, counts);
+    CUBE_GUARD_END
 }
 
 int cube_stats_hist_minmax(const float *ptr, const int64_t *dims, int32_t nbins,
                            cube_stats_t *out, uint64_t *counts)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     return run_sync(OP_MINMAX, ptr, dims, 0.f, 0.f, nbins, out, counts);
+    CUBE_GUARD_END
 }
 
 int cube_stats_async(const float *ptr, const int64_t *dims, cube_stats_t *dev_out,
                      void *stream)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     return run_async_entry(OP_STATS, ptr, dims, 0.f, 0.f, 1, dev_out, nullptr, stream);
+    CUBE_GUARD_END
 }
 
 int cube_hist_async(const float *ptr, const int64_t *dims, float lo, float hi, int32_t nbins,
                     uint64_t *dev_counts, void *stream)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     return run_async_entry(OP_HIST, ptr, dims, lo, hi, nbins, nullptr, dev_counts, stream);
+    CUBE_GUARD_END
 }
 
 int cube_stats_hist_async(const float *ptr, const int64_t *dims, float lo, float hi,
                           int32_t nbins, cube_stats_t *dev_out, uint64_t *dev_counts,
                           void *stream)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     return run_async_entry(OP_FUSED, ptr, dims, lo, hi, nbins, dev_out, dev_counts, stream);
+    CUBE_GUARD_END
 }
 
 int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims, int32_t nbins,
                                  cube_stats_t *dev_out, uint64_t *dev_counts, void *stream)
 {
+    CUBE_GUARD_BEGIN
     g_err.clear();
     return run_async_entry(OP_MINMAX, ptr, dims, 0.f, 0.f, nbins, dev_out, dev_counts, stream);
+    CUBE_GUARD_END
 }
 
 int cube_set_accum_mode(int32_t mode)

@@ -430,7 +430,9 @@ extern "C" {
 
 int cube_host_query(const cube_query_t *q, int64_t chunk_voxels)
 {
+    CUBE_GUARD_BEGIN
     return cube::host_query(q, chunk_voxels);
+    CUBE_GUARD_END
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
+
 #include "cubestats.h"
 
 namespace cube {
@@ -80,6 +82,21 @@ struct Plan {
     int threads, blocks, copies_log2, hist, unroll;
     size_t lds;
 };
+
+// No C++ exception leaves the C ABI: an entry point whose body may allocate
+// host memory wraps it in CUBE_GUARD_BEGIN ... CUBE_GUARD_END, which turns
+// std::bad_alloc into CUBE_ENOMEM and anything else into CUBE_EDEVICE.
+#define CUBE_GUARD_BEGIN try {
+#define CUBE_GUARD_END                                                          \
+    }                                                                           \
+    catch (const std::bad_alloc &)                                              \
+    {                                                                           \
+        return cube::fail(CUBE_ENOMEM, "host memory exhausted");                \
+    }                                                                           \
+    catch (...)                                                                 \
+    {                                                                           \
+        return cube::fail(CUBE_EDEVICE, "unexpected internal error");           \
+    }
 
 // Set the calling thread's error text and return `code`.
 int fail(int code, const char *fmt, ...);

@@ -290,6 +290,7 @@ extern "C" {
 int cube_project(const float *ptr, const int64_t *dims, float *mip, double *mom0,
                  uint32_t *nvalid, void *stream)
 {
+    CUBE_GUARD_BEGIN
     if (!mip && !mom0 && !nvalid) return fail(CUBE_EINVAL, "every output is NULL");
     Box b;
     int rc = check_box(ptr, dims, &b);
@@ -389,6 +390,7 @@ int cube_project(const float *ptr, const int64_t *dims, float *mip, double *mom0
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "projection merge");
     }
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 }  // extern "C"

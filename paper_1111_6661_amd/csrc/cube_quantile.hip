@@ -289,6 +289,7 @@ extern "C" {
 int cube_quantiles(const float *ptr, const int64_t *dims, const double *q, int32_t m,
                    double *out, uint64_t *n_valid)
 {
+    CUBE_GUARD_BEGIN
     if (!q || !out) return fail(CUBE_EINVAL, "q or out is NULL");
     if (m < 1 || m > CUBE_MAX_QUANTILES)
         return fail(CUBE_EINVAL, "m=%d outside [1, %d]", m, CUBE_MAX_QUANTILES);
@@ -305,6 +306,7 @@ int cube_quantiles(const float *ptr, const int64_t *dims, const double *q, int32
     }
     std::lock_guard<std::mutex> lk(g_qmu);
     return run_quantiles(b, q, m, out, n_valid);
+    CUBE_GUARD_END
 }
 
 }  // extern "C"

@@ -405,6 +405,7 @@ extern "C" {
 
 int cube_select(const float *ptr, const int64_t *dims, uint64_t rank, float *value)
 {
+    CUBE_GUARD_BEGIN
     if (!value) return fail(CUBE_EINVAL, "value is NULL");
     Box b;
     int rc = check_box(ptr, dims, &b);
@@ -413,10 +414,12 @@ int cube_select(const float *ptr, const int64_t *dims, uint64_t rank, float *val
     if (b.n == 0) return fail(CUBE_EINVAL, "empty box");
     std::lock_guard<std::mutex> lk(g_smu);
     return select_rank(b, rank, 0, value, nullptr);
+    CUBE_GUARD_END
 }
 
 int cube_median(const float *ptr, const int64_t *dims, double *median, uint64_t *n_valid)
 {
+    CUBE_GUARD_BEGIN
     if (!median) return fail(CUBE_EINVAL, "median is NULL");
     Box b;
     int rc = check_box(ptr, dims, &b);
@@ -434,6 +437,7 @@ int cube_median(const float *ptr, const int64_t *dims, double *median, uint64_t 
     if (rc) return rc;
     *median = n % 2 == 1 ? (double)a : ((double)a + (double)c) / 2.0;
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 }  // extern "C"

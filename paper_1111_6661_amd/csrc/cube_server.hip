@@ -244,6 +244,7 @@ extern "C" {
 int cube_server_create(int32_t mode, int32_t slots, int32_t max_batch, int64_t max_inflight_bytes,
                        int64_t tile_voxels, cube_server_t **out)
 {
+    CUBE_GUARD_BEGIN
     if (!out) return fail(CUBE_EINVAL, "out is NULL");
     if (mode != CUBE_SERVE_BATCHED && mode != CUBE_SERVE_PLAIN)
         return fail(CUBE_EINVAL, "unknown server mode %d", mode);
@@ -283,10 +284,12 @@ int cube_server_create(int32_t mode, int32_t slots, int32_t max_batch, int64_t m
     srv->worker = std::thread(worker_loop, srv);
     *out = srv;
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 int cube_server_submit(cube_server_t *srv, const cube_query_t *q, uint64_t *id)
 {
+    CUBE_GUARD_BEGIN
     if (!srv || !q || !id) return fail(CUBE_EINVAL, "NULL argument");
     // Host-side validation now; device-side checks happen at launch.
     Box box;
@@ -314,10 +317,12 @@ int cube_server_submit(cube_server_t *srv, const cube_query_t *q, uint64_t *id)
     *id = k;
     srv->cv_work.notify_one();
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 int cube_server_wait(cube_server_t *srv, uint64_t id, double timeout_s, double *latency_s)
 {
+    CUBE_GUARD_BEGIN
     if (!srv) return fail(CUBE_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(srv->mu);
     auto it = srv->entries.find(id);
@@ -338,11 +343,13 @@ int cube_server_wait(cube_server_t *srv, uint64_t id, double timeout_s, double *
     if (latency_s) *latency_s = e.t_done - e.t_submit;
     if (e.rc) return fail(e.rc, "%s", e.err);
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 int cube_server_latency(cube_server_t *srv, double *p50_s, double *p99_s, uint64_t *n_done,
                         int32_t reset)
 {
+    CUBE_GUARD_BEGIN
     if (!srv) return fail(CUBE_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(srv->mu);
     std::vector<double> v = srv->latencies;
@@ -362,6 +369,7 @@ int cube_server_latency(cube_server_t *srv, double *p50_s, double *p99_s, uint64
     if (p99_s) *p99_s = p99;
     if (reset) srv->latencies.clear();
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 void cube_server_destroy(cube_server_t *srv)

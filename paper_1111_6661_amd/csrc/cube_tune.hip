@@ -67,6 +67,7 @@ extern "C" {
 int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo, float hi,
                   int32_t nbins, int32_t reps, char *report, size_t report_cap)
 {
+    CUBE_GUARD_BEGIN
     if (kind != CUBE_Q_STATS && kind != CUBE_Q_HIST && kind != CUBE_Q_FUSED)
         return fail(CUBE_EINVAL, "autotune kinds: CUBE_Q_STATS, CUBE_Q_HIST, CUBE_Q_FUSED");
     if (reps < 1 || reps > 100) return fail(CUBE_EINVAL, "reps outside [1, 100]");
@@ -177,10 +178,12 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
         snprintf(report, report_cap, "%s", rep.c_str());
     }
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 int cube_tune_save(const char *path)
 {
+    CUBE_GUARD_BEGIN
     if (!path) return fail(CUBE_EINVAL, "path is NULL");
     FILE *f = fopen(path, "w");
     if (!f) return fail(CUBE_EINVAL, "cannot write %s", path);
@@ -199,11 +202,13 @@ int cube_tune_save(const char *path)
     fprintf(f, "\n]}\n");
     fclose(f);
     return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 // Minimal reader for the format cube_tune_save writes: one entry per line.
 int cube_tune_load(const char *path)
 {
+    CUBE_GUARD_BEGIN
     if (!path) return fail(CUBE_EINVAL, "path is NULL");
     FILE *f = fopen(path, "r");
     if (!f) return fail(CUBE_EINVAL, "cannot read %s", path);
@@ -239,6 +244,7 @@ int cube_tune_load(const char *path)
     std::lock_guard<std::mutex> lk(g_tmu);
     for (auto &kv : t) g_table[kv.first] = kv.second;
     return n;
+    CUBE_GUARD_END
 }
 
 void cube_tune_clear(void)
