@@ -405,6 +405,7 @@ int cube_batch_create(cube_batch_t **out)
 
 void cube_batch_destroy(cube_batch_t *b)
 {
+    CUBE_GUARD_BEGIN
     if (!b) return;
     {
         std::lock_guard<std::mutex> lk(b->mu);
@@ -415,6 +416,7 @@ void cube_batch_destroy(cube_batch_t *b)
         if (b->h_done) hipHostFree(b->h_done);
     }
     delete b;
+    CUBE_GUARD_VOID_END
 }
 
 int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads)

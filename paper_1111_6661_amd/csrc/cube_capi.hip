@@ -643,12 +643,14 @@ int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_
 
 void cube_shutdown(void)
 {
+    CUBE_GUARD_BEGIN
     host_release();
     project_release();
     quant_release();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &kv : g_ws) free_ws(kv.second);
     g_ws.clear();
+    CUBE_GUARD_VOID_END
 }
 
 }  // extern "C"

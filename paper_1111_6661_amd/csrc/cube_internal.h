@@ -98,6 +98,13 @@ struct Plan {
         return cube::fail(CUBE_EDEVICE, "unexpected internal error");           \
     }
 
+// The same for entry points that return nothing: an exception is dropped.
+#define CUBE_GUARD_VOID_END                                                     \
+    }                                                                           \
+    catch (...)                                                                 \
+    {                                                                           \
+    }
+
 // Set the calling thread's error text and return `code`.
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);

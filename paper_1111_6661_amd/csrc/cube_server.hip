@@ -374,6 +374,7 @@ int cube_server_latency(cube_server_t *srv, double *p50_s, double *p99_s, uint64
 
 void cube_server_destroy(cube_server_t *srv)
 {
+    CUBE_GUARD_BEGIN
     if (!srv) return;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
@@ -389,6 +390,7 @@ void cube_server_destroy(cube_server_t *srv)
     }
     delete srv->policy;
     delete srv;
+    CUBE_GUARD_VOID_END
 }
 
 }  // extern "C"

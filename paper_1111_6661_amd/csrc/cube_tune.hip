@@ -249,8 +249,10 @@ int cube_tune_load(const char *path)
 
 void cube_tune_clear(void)
 {
+    CUBE_GUARD_BEGIN
     std::lock_guard<std::mutex> lk(g_tmu);
     g_table.clear();
+    CUBE_GUARD_VOID_END
 }
 
 }  // extern "C"
