@@ -25,6 +25,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cubeoracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
+ORACLE_ABI = 2   # layout of the sweep records; equals ORACLE_ABI in cubeoracle.c
+
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
           "-fno-unsafe-math-optimizations", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
@@ -41,7 +43,8 @@ class _Sweep1(C.Structure):
     _fields_ = [("n_total", C.c_uint64), ("n_valid", C.c_uint64), ("n_nan", C.c_uint64),
                 ("min", C.c_float), ("max", C.c_float),
                 ("sum", C.c_double), ("sum_c", C.c_double),
-                ("sabs", C.c_double), ("sabs_c", C.c_double)]
+                ("sabs", C.c_double), ("sabs_c", C.c_double),
+                ("n_pinf", C.c_uint64), ("n_ninf", C.c_uint64)]
 
 
 class _Sweep2(C.Structure):
@@ -82,6 +85,9 @@ class Oracle:
         i64, f32, f64 = C.c_int64, C.c_float, C.c_double
         P = C.c_void_p
         lib.oracle_abi_version.restype = C.c_int
+        if lib.oracle_abi_version() != ORACLE_ABI:
+            raise RuntimeError(f"{path}: oracle ABI {lib.oracle_abi_version()}, "
+                               f"expected {ORACLE_ABI}: rebuild it (oracle.build())")
         lib.oracle_sweep1_init.argtypes = [C.POINTER(_Sweep1)]
         lib.oracle_sweep1.argtypes = [C.POINTER(_Sweep1), P, i64, i64, i64, i64, i64]
         lib.oracle_sweep1.restype = C.c_int

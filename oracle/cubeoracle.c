@@ -23,6 +23,14 @@
  *   std          : sqrt(m2 / n_valid)   (population standard deviation)
  *   mean_abs     : (1/n_valid) * sum |x|  (only used to scale tolerances)
  *
+ *   These sums are taken over the extended reals, as IEEE arithmetic defines
+ *   them for +-Inf, not as a rounding artifact of any summation order: with
+ *   +Inf among the valid voxels (and no -Inf) the mean is +Inf, with -Inf
+ *   alone it is -Inf, with both it is NaN (Inf - Inf); mean_abs is then +Inf;
+ *   and since some deviation x - mean is then Inf - Inf or an infinite mean
+ *   minus a finite x, m2 and std are NaN.  The finite voxels are summed
+ *   apart from the infinities so that the finite case is exact as before.
+ *
  *   select(k)    : the valid voxel of rank k (0-based) in the order by value
  *                  with -0 before +0; median = select((n-1)/2) for odd
  *                  n_valid, the FP64 mean of select(n/2-1) and select(n/2)
@@ -75,13 +83,14 @@
 #error "the oracle must not be built with fast-math"
 #endif
 
-#define ORACLE_ABI 1
+#define ORACLE_ABI 2
 
 typedef struct {
     uint64_t n_total, n_valid, n_nan;
     float min, max;
     double sum, sum_c;   /* Neumaier pair for sum x   */
     double sabs, sabs_c; /* Neumaier pair for sum |x| */
+    uint64_t n_pinf, n_ninf; /* valid voxels equal to +Inf and to -Inf */
 } oracle_sweep1_t;
 
 typedef struct {
@@ -158,16 +167,25 @@ int oracle_sweep1(oracle_sweep1_t *s, const float *p, int64_t nx, int64_t ny,
                     if (before(s->max, v)) s->max = v;
                 }
                 s->n_valid++;
+                if (isinf(v)) {
+                    /* kept apart: the sum of the finite voxels stays finite */
+                    if (v > 0) s->n_pinf++; else s->n_ninf++;
+                    continue;
+                }
                 neumaier_add(&s->sum, &s->sum_c, (double)v);
                 neumaier_add(&s->sabs, &s->sabs_c, fabs((double)v));
             }
     return 0;
 }
 
-/* The mean that sweep 2 needs, from a finished sweep 1. */
+/* The mean that sweep 2 needs, from a finished sweep 1 (extended reals:
+ * +Inf, -Inf or NaN when infinite voxels are present). */
 double oracle_sweep1_mean(const oracle_sweep1_t *s)
 {
     if (s->n_valid == 0) return NAN;
+    if (s->n_pinf && s->n_ninf) return NAN;
+    if (s->n_pinf) return INFINITY;
+    if (s->n_ninf) return -INFINITY;
     return (s->sum + s->sum_c) / (double)s->n_valid;
 }
 
@@ -205,6 +223,13 @@ void oracle_finish(const oracle_sweep1_t *a, const oracle_sweep2_t *b,
     }
     double n = (double)a->n_valid;
     out->mean = oracle_sweep1_mean(a);
+    if (a->n_pinf || a->n_ninf) {
+        /* an infinite voxel: |x| sums to +Inf, and a deviation x - mean is
+         * Inf - Inf or infinite, so m2 and std are NaN (extended reals) */
+        out->mean_abs = INFINITY;
+        out->m2 = out->std = NAN;
+        return;
+    }
     out->mean_abs = (a->sabs + a->sabs_c) / n;
     double dev = b->dev + b->dev_c;
     double m2 = (b->sq + b->sq_c) - dev * dev / n;

@@ -9,7 +9,8 @@ show that a plausible mistake anywhere in the oracle fails at least one pin.
 What pins what:
   * mean / m2 / std: a textbook worked example (golden file), exact rational
     arithmetic with ``fractions`` and the ``statistics`` module, closed forms
-    of constant and integer-ramp cubes, and the merge identity of two halves.
+    of constant and integer-ramp cubes, the merge identity of two halves, and
+    numpy's extended-real mean and std for boxes holding +-Inf.
   * min / max / NaN count: numpy's nanmin / nanmax / isnan, signed zeros by
     bit pattern, all-NaN, single voxel, NaN payloads.
   * histogram: closed forms (integer ramp with power-of-two bin width;
@@ -120,6 +121,51 @@ def pin_merge(o):
     assert whole.n_valid == n
     assert abs(whole.mean - mean) <= 1e-13 * abs(mean)
     assert abs(whole.m2 - m2) <= 1e-12 * m2
+
+
+def pin_infinite_moments(o):
+    """Moments with +-Inf among the valid voxels, over the extended reals:
+    numpy's float64 mean and population std of the valid voxels (IEEE
+    arithmetic on infinities, an independent routine) fix them, and the
+    finite voxels around them must not disturb the reading.  The infinite
+    voxels are still ordinary values for the extrema and counts."""
+    import warnings
+    cases = [
+        ([1.0, np.inf, 2.0], np.inf),
+        ([np.inf], np.inf),
+        ([np.inf, np.inf, np.nan], np.inf),
+        ([-np.inf, 1.0, np.nan, -5.0], -np.inf),
+        ([np.inf, -np.inf], None),
+        ([3.0, np.nan, -np.inf, 2.5, np.inf, 1e30], None),
+    ]
+    for vals, want_mean in cases:
+        a = np.array(vals, dtype=np.float32)
+        v = a[~np.isnan(a)].astype(np.float64)
+        with np.errstate(invalid="ignore"), warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            np_mean, np_std = float(np.mean(v)), float(np.std(v))
+            np_mabs = float(np.mean(np.abs(v)))
+        s = o.stats(a)
+        if want_mean is None:
+            assert math.isnan(np_mean) and math.isnan(s.mean), (vals, s.mean)
+        else:
+            assert np_mean == want_mean and s.mean == want_mean, (vals, s.mean, np_mean)
+        assert math.isnan(np_std) and math.isnan(s.std) and math.isnan(s.m2), (vals, s.std)
+        assert s.mean_abs == np_mabs == np.inf, (vals, s.mean_abs)
+        assert s.n_valid == v.size and s.n_nan == a.size - v.size
+        assert s.min == v.min() and s.max == v.max()
+    # a large finite cube with one +Inf: +Inf mean; without it, finite again
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal(10_000).astype(np.float32)
+    fin = o.stats(b)
+    b[4321] = np.inf
+    s = o.stats(b)
+    assert s.mean == np.inf and math.isnan(s.std) and s.max == np.inf
+    assert math.isfinite(fin.mean) and math.isfinite(fin.std)
+    # streamed in pieces, with the infinity in the second piece only
+    pieces = lambda: iter((b[:5000], b[5000:]))
+    t = o.stats_pieces(pieces)
+    assert t.mean == np.inf and math.isnan(t.std) and t.n_valid == b.size
 
 
 # ------------------------------------------------------------ extrema / NaN
@@ -465,7 +511,7 @@ def pin_project(o):
         assert np.array_equal(u, v, equal_nan=True)
 
 
-ALL_PINS = [pin_textbook, pin_exact_rational, pin_closed_forms, pin_merge,
+ALL_PINS = [pin_textbook, pin_exact_rational, pin_closed_forms, pin_merge, pin_infinite_moments,
             pin_extrema_nan, pin_strided, pin_hist_ramp, pin_hist_unit_scale,
             pin_hist_edges, pin_hist_subnormal, pin_hist_rounding_model, pin_hist_numpy,
             pin_hist_invariants, pin_hist_validation, pin_select, pin_quantiles,

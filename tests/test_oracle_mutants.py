@@ -33,6 +33,10 @@ MUTANTS = {
     "deviation_sign": ("double d = (double)v - mean;", "double d = mean + (double)v;"),
     "sample_std": ("out->std = sqrt(m2 / n);", "out->std = sqrt(m2 / (n - 1.0));"),
     "mean_abs_signed": ("fabs((double)v));", "(double)v);"),
+    "inf_through_compensation": ("if (isinf(v)) {\n                    /* kept apart",
+                                 "if (0) {\n                    /* kept apart"),
+    "inf_both_signs_not_nan": ("if (s->n_pinf && s->n_ninf) return NAN;", ""),
+    "inf_std_finite": ("out->m2 = out->std = NAN;\n        return;", "out->m2 = out->std = 0.0;"),
     "clamp_off_by_one": ("if (b > nbins - 1) b = nbins - 1;", "if (b > nbins) b = nbins;"),
     "below_above_swapped": ("counts[nbins]++;\n                } else if (v > hi) {\n                    counts[nbins + 1]++;",
                             "counts[nbins + 1]++;\n                } else if (v > hi) {\n                    counts[nbins]++;"),
