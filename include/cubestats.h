@@ -159,10 +159,13 @@ CUBE_API int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims,
                                  uint64_t *dev_counts, void *stream);
 
 /*
- * Precision mode of the moments for later calls from any thread (the
- * FP32-only modes exist to compare against; only CUBE_ACCUM_FP64MERGE meets
- * the 1e-6 relative bound on hard inputs).  Returns the previous mode, or
- * CUBE_EINVAL for an unknown mode.
+ * Precision mode of the moments for later single-box calls from the CALLING
+ * THREAD only (each thread starts with CUBE_ACCUM_FP64MERGE; other threads,
+ * batches and the server are unaffected: batched and served queries always
+ * use CUBE_ACCUM_FP64MERGE).  The FP32-only modes exist to compare against;
+ * only CUBE_ACCUM_FP64MERGE meets the 1e-6 relative bound on hard inputs.
+ * Returns the previous mode of the thread, or CUBE_EINVAL for an unknown
+ * mode.
  */
 CUBE_API int cube_set_accum_mode(int32_t mode);
 
@@ -171,7 +174,8 @@ CUBE_API int cube_set_accum_mode(int32_t mode);
  * for experiments: threads per block (256, 512 or 1024; 0 = automatic),
  * blocks per launch (0 = automatic), histogram sub-copies per block (1..32,
  * a power of two; 0 = automatic), float4 loads per lane per pipelined tile
- * (2 or 4; 0 = automatic).  Applies to later calls from any thread.
+ * (2 or 4; 0 = automatic).  Applies to later single-box calls from the
+ * CALLING THREAD only (each thread starts with all zeros).
  * Results do not depend on the launch shape except for the rounding of the
  * moments (the merge order follows the grid).
  */
@@ -328,9 +332,12 @@ CUBE_API int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t 
 #define CUBE_ORDER_SMALLEST_FIRST 1
 CUBE_API int cube_batch_set_order(cube_batch_t *b, int32_t order);
 /* 1 when query i of the last launch of b has completed (its device outputs
- * are final), else 0; reads a host-mapped flag that the kernel writes, with
- * no GPU call.  Valid after cube_batch_enqueue and cube_batch_relaunch (a
- * graph replay repeats the generation it captured, so use the stream). */
+ * are final), 0 while it has not, and CUBE_EDEVICE when it completed as
+ * failed: a two-pass query whose bounded wait for its own [min, max] range
+ * expired (its histogram is then incomplete; other queries are unaffected).
+ * Reads a host-mapped flag that the kernel writes, with no GPU call.  Valid
+ * after cube_batch_enqueue and cube_batch_relaunch (a graph replay repeats
+ * the generation it captured, so use the stream). */
 CUBE_API int cube_batch_query_done(cube_batch_t *b, int32_t i);
 /* Launch the last enqueued work list again (no host work, no copies).
  * Launches of one batch object are ordered: one on another stream than the
@@ -339,8 +346,14 @@ CUBE_API int cube_batch_relaunch(cube_batch_t *b, void *stream);
 /* Same as cube_batch_relaunch through a captured HIP graph: the first call
  * after an enqueue captures the launch, later calls replay it on any stream. */
 CUBE_API int cube_batch_graph_launch(cube_batch_t *b, void *stream);
-/* Wait for the batch and report whether every two-pass query completed
- * (CUBE_EDEVICE if a query's bounded wait for its range expired). */
+/* Wait for the batch and report whether every two-pass query of the
+ * launches since the last check completed: CUBE_EDEVICE if a query's bounded
+ * wait for its range expired (reported once; the flag is then cleared).
+ * A range published by one launch never releases the second phase of a
+ * later launch, so the launches after a failure run normally.  Test knob:
+ * CUBE_FAULT_INJECT="expire:N[,M...]" (read by cube_batch_create): in the
+ * batch's launches N, M, ... (counted from 1 over enqueues and relaunches;
+ * graph replays excluded) every range wait gives up at once. */
 CUBE_API int cube_batch_check(cube_batch_t *b);
 /* Synchronous convenience: create, enqueue on the default stream, check,
  * destroy. */
@@ -388,11 +401,16 @@ typedef struct cube_server cube_server_t;
 /* slots: 1..16 concurrent batches; max_batch: queries per batch (1..4096);
  * max_inflight_bytes: device scratch budget (>= 4096); tile_voxels: 0 =
  * each query's automatic size (see cube_batch_set_tile), else 4096..2^30.  The calling thread's current device is used.
- * Failure handling can be tested with the environment variable
- * CUBE_FAULT_INJECT="launch:N[,M...]" (read at creation): the server's
- * launches number N, M, ... (counted from 1) fail on the host before any
- * work is queued; the queries of that batch complete with CUBE_EDEVICE and
- * the server goes on serving. */
+ * A batch whose launch fails, or whose completion event reports a device
+ * error, completes its unfinished queries with CUBE_EDEVICE and frees its
+ * slot; a two-pass query whose range wait expired completes with
+ * CUBE_EDEVICE alone.  The server goes on serving either way.  Failure
+ * handling can be tested with the environment variable CUBE_FAULT_INJECT
+ * (read at creation; launches counted from 1 per server): "launch:N[,M...]"
+ * fails launches N, M, ... on the host before any work is queued;
+ * "event:N" makes the completion event of launch N report an error (the
+ * work itself runs to its end); "expire:N" reaches the slots' batches
+ * (see cube_batch_check).  Items combine: "launch:2,event:4,expire:1". */
 CUBE_API int cube_server_create(int32_t mode, int32_t slots, int32_t max_batch,
                                 int64_t max_inflight_bytes, int64_t tile_voxels,
                                 cube_server_t **out);

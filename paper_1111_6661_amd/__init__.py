@@ -466,7 +466,12 @@ class Batch:
         _check(load().cube_batch_set_order(self._h, order))
 
     def query_done(self, i: int) -> bool:
-        return bool(load().cube_batch_query_done(self._h, i))
+        """True once query i of the last launch is complete; raises CubeError
+        if it completed as failed."""
+        rc = load().cube_batch_query_done(self._h, i)
+        if rc < 0:
+            raise CubeError(rc, last_error())
+        return bool(rc)
 
     def relaunch(self, stream: int = 0) -> None:
         _check(load().cube_batch_relaunch(self._h, C.c_void_p(stream)))

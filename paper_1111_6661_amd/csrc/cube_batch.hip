@@ -16,10 +16,17 @@
 //
 // Progress: a second-phase tile waits only for its own query's first phase,
 // whose tiles all come earlier in the list and were therefore taken by
-// running blocks that never wait; the wait is bounded anyway (an error flag
-// is raised and the tile skipped if it ever expires).  Results of a query do
-// not depend on the other queries of the batch (its tiling and merge order
-// are its own), so a query gives the same bits alone and in any mix.
+// running blocks that never wait; the wait is bounded anyway.  If it ever
+// expires the tile is skipped, the batch's error flag and the query's own
+// failure flag are raised, and the query completes marked as failed (its
+// histogram is incomplete); the other queries are unaffected.  The range
+// flag a query's first phase raises carries the launch's epoch (a counter
+// the last block of every launch advances), so a flag left up by an earlier
+// launch -- or raised after its query's second phase already gave up --
+// never releases the tiles of a later launch, graph replays included.
+// Results of a query do not depend on the other queries of the batch (its
+// tiling and merge order are its own), so a query gives the same bits alone
+// and in any mix.
 #include <stdlib.h>
 #include <string.h>
 
@@ -46,8 +53,10 @@ struct BatchItem {                 // read-only during a launch
     unsigned long long *counts;
 };
 
-struct BatchState {                // zero between launches
-    unsigned int done1, done2, ready, pad;
+struct BatchState {                // counters zero between launches
+    unsigned int done1, done2;
+    unsigned int ready;            // epoch tag of the launch whose range is published
+    unsigned int failed;           // a second-phase tile gave up (this launch)
     HistRange range;
 };
 
@@ -64,11 +73,15 @@ struct BatchArgs {
     WaveRec *recs;
     unsigned long long *acc;
     unsigned int *ctl;             // [0] next tile, [1] exit ticket, [2] error flag
+                                   // (sticky until read by the host), [3] epoch
     int32_t accum_mode;
-    unsigned int spin_limit;
-    unsigned int *done_flags;      // host-mapped, one per query: `gen` once done
-    unsigned int gen;
+    unsigned int spin_limit;       // polls of a range wait; 0 = give up at once
+    unsigned int *done_flags;      // host-mapped, one per query: `gen` once done,
+                                   // with DONE_FAILED set if the query failed
+    unsigned int gen;              // 1 .. 2^31 - 1
 };
+
+constexpr unsigned int DONE_FAILED = 0x80000000u;
 
 constexpr int BATCH_UNROLL = 4;
 
@@ -83,9 +96,17 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
 {
     extern __shared__ unsigned int lds[];
     __shared__ int s_tile;
-    __shared__ unsigned int s_flag;
+    __shared__ unsigned int s_flag, s_tag;
     __shared__ HistRange s_range;
     const int tid = threadIdx.x, wid = tid >> 6, nw = blockDim.x >> 6;
+
+    // This launch's epoch tag (never 0).  The epoch only changes when the
+    // last block leaves, after every block has read it here.
+    if (tid == 0)
+        s_tag = (__hip_atomic_load(&a.ctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                 0x7fffffffu) + 1u;
+    __syncthreads();
+    const unsigned int tag = s_tag;
 
     while (true) {
         if (tid == 0) s_tile = (int)atomicAdd(&a.ctl[0], 1u);
@@ -107,14 +128,17 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                 unsigned int spins = 0;
                 s_flag = 1u;
                 // Relaxed polls, then one acquire fence once the flag is up.
-                while (__hip_atomic_load(&st->ready, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-                    __builtin_amdgcn_s_sleep(8);
-                    if (++spins > a.spin_limit) {
+                // A spin limit of 0 (a test setting) gives up at once.
+                while (a.spin_limit == 0u ||
+                       __hip_atomic_load(&st->ready, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) != tag) {
+                    if (a.spin_limit == 0u || ++spins > a.spin_limit) {
                         atomicOr(&a.ctl[2], 1u);
+                        atomicOr(&st->failed, 1u);
                         s_flag = 0u;
                         break;
                     }
+                    __builtin_amdgcn_s_sleep(8);
                 }
                 if (s_flag) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -176,25 +200,29 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
             __syncthreads();
             if (tid == 0) {
                 bool finished = true;
+                unsigned int failed = 0u;
                 if (tile.phase == 1) {
                     st->done1 = 0u;
                     if (it.kind == BQ_MINMAX) {
                         // A release store: it orders the range (and, over
                         // the barrier, every thread's writes) before the flag.
                         finished = false;
-                        __hip_atomic_store(&st->ready, 1u, __ATOMIC_RELEASE,
+                        __hip_atomic_store(&st->ready, tag, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     }
                 } else {
-                    // Every second-phase tile of this query has read the
-                    // range: the query's state returns to zero.
+                    // Every second-phase tile of this query has arrived: its
+                    // counters return to zero.  The range flag needs no reset
+                    // (the next launch waits for its own tag).
+                    failed = st->failed;
+                    st->failed = 0u;
                     st->done2 = 0u;
-                    st->ready = 0u;
                 }
                 if (finished && a.done_flags) {
                     // The query's outputs are complete: tell the host (a
                     // system-scope release store orders the outputs first).
-                    __hip_atomic_store(&a.done_flags[tile.item], a.gen, __ATOMIC_RELEASE,
+                    __hip_atomic_store(&a.done_flags[tile.item],
+                                       a.gen | (failed ? DONE_FAILED : 0u), __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_SYSTEM);
                 }
             }
@@ -202,10 +230,13 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         __syncthreads();
     }
 
-    // The last block to leave returns the work counters to zero.
+    // The last block to leave returns the work counters to zero and starts
+    // the next epoch.
     if (tid == 0 && atomicAdd(&a.ctl[1], 1u) == gridDim.x - 1) {
         a.ctl[0] = 0u;
         a.ctl[1] = 0u;
+        __hip_atomic_store(&a.ctl[3], (tag & 0x7fffffffu), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -246,6 +277,8 @@ struct cube_batch {
     unsigned int *d_done = nullptr; // the same memory as the device sees it
     size_t cap_done = 0;
     unsigned int gen = 0;
+    uint64_t launches = 0;          // launches of this batch so far
+    std::vector<uint64_t> expire;   // test knob: launches whose range waits give up
     int order = 0;                  // 0 largest queries first, 1 smallest first
     bool have_work = false;
     BatchArgs args;
@@ -373,11 +406,15 @@ hipError_t mark_launched(cube_batch *b, hipStream_t s)
 
 int launch_batch(cube_batch *b, hipStream_t s)
 {
-    // A new generation per launch: completion flags of earlier launches
-    // never read as done.
-    if (++b->gen == 0) ++b->gen;
+    // A new generation per launch (31 bits; the top bit of a flag marks a
+    // failed query): completion flags of earlier launches never read as done.
+    b->gen = (b->gen + 1u) & 0x7fffffffu;
+    if (b->gen == 0) b->gen = 1u;
     b->args.gen = b->gen;
     BatchArgs a = b->args;
+    ++b->launches;
+    for (uint64_t n : b->expire)
+        if (n == b->launches) a.spin_limit = 0u;
     void *args[] = {&a};
     hipError_t e = order_after_previous(b, s);
     if (e != hipSuccess) return hip_fail(e, "batch ordering");
@@ -398,6 +435,10 @@ int cube_batch_create(cube_batch_t **out)
     if (!out) return fail(CUBE_EINVAL, "out is NULL");
     cube_batch *b = new cube_batch;
     hipGetDevice(&b->device);
+    // Test knob: CUBE_FAULT_INJECT="expire:N[,M...]": in launches N, M, ...
+    // of this batch (counted from 1; enqueues and relaunches) every range
+    // wait gives up at once, so every two-pass query of them fails.
+    b->expire = fault_inject("expire");
     *out = b;
     return CUBE_OK;
     CUBE_GUARD_END
@@ -599,7 +640,12 @@ int cube_batch_set_order(cube_batch_t *b, int32_t order)
 int cube_batch_query_done(cube_batch_t *b, int32_t i)
 {
     if (!b || i < 0 || (size_t)i >= b->cap_done || !b->h_done) return 0;
-    return __atomic_load_n(&b->h_done[i], __ATOMIC_ACQUIRE) == b->args.gen ? 1 : 0;
+    const unsigned int v = __atomic_load_n(&b->h_done[i], __ATOMIC_ACQUIRE);
+    if ((v & ~DONE_FAILED) != b->args.gen) return 0;
+    if (v & DONE_FAILED)
+        return fail(CUBE_EDEVICE, "query %d: its bounded wait for its [min, max] range "
+                                  "expired; its histogram is incomplete", i);
+    return 1;
 }
 
 int cube_batch_relaunch(cube_batch_t *b, void *stream)
@@ -667,8 +713,14 @@ int cube_batch_check(cube_batch_t *b)
         return hip_fail(e, "batch synchronize");
     if ((e = hipMemcpy(ctl, b->d_ctl, sizeof ctl, hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(e, "batch status copy");
-    if (ctl[2]) return fail(CUBE_EDEVICE, "a batched two-pass query timed out waiting for its "
-                                          "range; its histogram is incomplete");
+    if (ctl[2]) {
+        // Reported once: the flag is cleared for the launches that follow.
+        const unsigned int zero = 0u;
+        if ((e = hipMemcpy(b->d_ctl + 2, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "batch status reset");
+        return fail(CUBE_EDEVICE, "a batched two-pass query timed out waiting for its "
+                                  "range; its histogram is incomplete");
+    }
     return CUBE_OK;
 }
 

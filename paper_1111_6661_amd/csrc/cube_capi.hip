@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -34,18 +35,46 @@ int hip_fail(hipError_t e, const char *what)
     return fail(CUBE_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
-std::atomic<int> g_accum{CUBE_ACCUM_FP64MERGE};
+std::vector<uint64_t> fault_inject(const char *kind)
+{
+    std::vector<uint64_t> out;
+    const char *env = getenv("CUBE_FAULT_INJECT");
+    if (!env) return out;
+    const size_t klen = strlen(kind);
+    bool match = false;
+    for (const char *p = env; *p;) {
+        const char *end = strchr(p, ',');
+        const size_t len = end ? (size_t)(end - p) : strlen(p);
+        const char *colon = (const char *)memchr(p, ':', len);
+        const char *num = p;
+        if (colon) {
+            match = (size_t)(colon - p) == klen && strncmp(p, kind, klen) == 0;
+            num = colon + 1;
+        }
+        char *stop = nullptr;
+        const unsigned long long v = strtoull(num, &stop, 10);
+        if (match && stop != num && stop == p + len) out.push_back((uint64_t)v);
+        if (!end) break;
+        p = end + 1;
+    }
+    return out;
+}
 
-int accum_mode() { return g_accum.load(); }
+// The precision mode and the launch-shape override belong to the calling
+// thread: a call never takes a setting another thread made (the server's
+// worker, for one, always runs with the defaults).
+thread_local int g_accum = CUBE_ACCUM_FP64MERGE;
 
-std::atomic<int> g_threads{0}, g_blocks{0}, g_copies{0}, g_unroll{0};
+int accum_mode() { return g_accum; }
+
+thread_local int g_threads = 0, g_blocks = 0, g_copies = 0, g_unroll = 0;
 
 void get_launch(int *threads, int *blocks, int *copies, int *unroll)
 {
-    *threads = g_threads.load();
-    *blocks = g_blocks.load();
-    *copies = g_copies.load();
-    *unroll = g_unroll.load();
+    *threads = g_threads;
+    *blocks = g_blocks;
+    *copies = g_copies;
+    *unroll = g_unroll;
 }
 
 constexpr int MAX_BLOCKS = 4096;
@@ -149,6 +178,24 @@ int cu_count()
 
 // ---------------------------------------------------------------- validation
 
+// One past the last voxel of a non-empty box, in floats from its first:
+// (nz-1)*sz + (ny-1)*sy + nx, with every product and sum checked.  False
+// when it does not fit in 2^62 floats, so that neither it nor its size in
+// bytes can wrap around (a wrapped extent would let a box reaching far past
+// its allocation pass the bounds check, and the kernel would fault).
+static bool box_end_floats(const Box &b, uint64_t *end)
+{
+    const uint64_t sy = b.ny > 1 ? (uint64_t)b.sy : 0, sz = b.nz > 1 ? (uint64_t)b.sz : 0;
+    uint64_t ey = 0, ez = 0, e = 0;
+    if (__builtin_mul_overflow((uint64_t)(b.ny - 1), sy, &ey) ||
+        __builtin_mul_overflow((uint64_t)(b.nz - 1), sz, &ez) ||
+        __builtin_add_overflow(ey, ez, &e) || __builtin_add_overflow(e, (uint64_t)b.nx, &e) ||
+        e > ((uint64_t)1 << 62))
+        return false;
+    *end = e;
+    return true;
+}
+
 int check_box(const float *ptr, const int64_t *dims, Box *b)
 {
     if (!dims) return fail(CUBE_EINVAL, "dims is NULL");
@@ -160,9 +207,11 @@ int check_box(const float *ptr, const int64_t *dims, Box *b)
         return fail(CUBE_EINVAL, "negative extent (%lld, %lld, %lld)", (long long)b->nx,
                     (long long)b->ny, (long long)b->nz);
     b->sy = dims[3] == 0 ? b->nx : dims[3];
-    b->sz = dims[4] == 0 ? b->sy * b->ny : dims[4];
+    b->sz = dims[4];
     if (b->nx == 0 || b->ny == 0 || b->nz == 0) {
         b->n = 0;
+        // nothing is read; the dense plane pitch only if it is representable
+        if (b->sz == 0 && __builtin_mul_overflow(b->sy, b->ny, &b->sz)) b->sz = 0;
         return CUBE_OK;
     }
     if (b->nx > (int64_t)1 << 40 || b->ny > (int64_t)1 << 40 || b->nz > (int64_t)1 << 40)
@@ -170,11 +219,21 @@ int check_box(const float *ptr, const int64_t *dims, Box *b)
     if (b->ny > 1 && b->sy < b->nx)
         return fail(CUBE_EINVAL, "row pitch sy=%lld < nx=%lld", (long long)b->sy,
                     (long long)b->nx);
-    if (b->nz > 1 && b->sz < (b->ny > 1 ? b->sy * (b->ny - 1) : 0) + b->nx)
+    // The plane's own extent, (ny-1)*sy + nx, checked (sy >= nx >= 1 here
+    // when ny > 1), then the dense plane pitch sy*ny when sz is 0.
+    int64_t plane = b->nx, dense = b->sy;
+    if (b->ny > 1 && (__builtin_mul_overflow(b->sy, b->ny - 1, &plane) ||
+                      __builtin_add_overflow(plane, b->nx, &plane) ||
+                      __builtin_mul_overflow(b->sy, b->ny, &dense)))
+        return fail(CUBE_EINVAL, "row pitch sy=%lld too large", (long long)b->sy);
+    if (b->sz == 0) b->sz = dense;
+    if (b->nz > 1 && b->sz < plane)
         return fail(CUBE_EINVAL, "plane pitch sz=%lld overlaps the previous plane",
                     (long long)b->sz);
-    if (b->ny > 1 && b->sy < 0) return fail(CUBE_EINVAL, "negative row pitch");
-    if (b->nz > 1 && b->sz < 0) return fail(CUBE_EINVAL, "negative plane pitch");
+    uint64_t end = 0;
+    if (!box_end_floats(*b, &end))
+        return fail(CUBE_EINVAL, "box extent overflows (pitches sy=%lld, sz=%lld)",
+                    (long long)b->sy, (long long)b->sz);
     b->n = (uint64_t)b->nx * (uint64_t)b->ny * (uint64_t)b->nz;
     if (!ptr) return fail(CUBE_EINVAL, "data pointer is NULL");
     if ((uintptr_t)ptr & 3) return fail(CUBE_EINVAL, "data pointer is not 4-byte aligned");
@@ -203,11 +262,10 @@ int check_box_device(const Box *b)
         hipGetLastError();
         return fail(CUBE_EINVAL, "cannot find the allocation of the data pointer");
     }
-    const uint64_t last = (uint64_t)(b->nz - 1) * (uint64_t)(b->nz > 1 ? b->sz : 0) +
-                          (uint64_t)(b->ny - 1) * (uint64_t)(b->ny > 1 ? b->sy : 0) +
-                          (uint64_t)b->nx;  // one past the last voxel, in floats
-    const uintptr_t end = (uintptr_t)ptr + last * 4u;
-    if (end > (uintptr_t)base + size || end < (uintptr_t)ptr)
+    uint64_t last = 0;  // one past the last voxel, in floats (checked, < 2^62)
+    if (!box_end_floats(*b, &last)) return fail(CUBE_EINVAL, "box extent overflows");
+    const uint64_t room = (uint64_t)((uintptr_t)base + size - (uintptr_t)ptr);  // bytes
+    if ((uintptr_t)ptr < (uintptr_t)base || last > room / 4u)
         return fail(CUBE_EINVAL, "box extends past the end of its allocation");
     int dev = 0;
     hipGetDevice(&dev);
@@ -271,8 +329,8 @@ void collapse(const Box &b, Geom *g)
 int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
 {
     collapse(b, &p->g);
-    int threads = g_threads.load(), unroll = g_unroll.load(), copies_req = g_copies.load();
-    long long blocks = g_blocks.load();
+    int threads = g_threads, unroll = g_unroll, copies_req = g_copies;
+    long long blocks = g_blocks;
     // With no explicit shape, use the autotuner's choice for this class.
     TunedShape ts;
     const int kind = stats ? (hist_kind_req ? CUBE_Q_FUSED : CUBE_Q_STATS) : CUBE_Q_HIST;
@@ -393,7 +451,7 @@ PassArgs base_args(const Workspace *w, const Plan &p, int nbins)
     a.recs = w->recs;
     a.ticket = w->ticket;
     a.hist_acc = w->hist_acc;
-    a.accum_mode = g_accum.load();
+    a.accum_mode = g_accum;
     return a;
 }
 
@@ -622,7 +680,9 @@ int cube_set_accum_mode(int32_t mode)
 {
     if (mode != CUBE_ACCUM_FP64MERGE && mode != CUBE_ACCUM_KAHAN32 && mode != CUBE_ACCUM_NAIVE32)
         return fail(CUBE_EINVAL, "unknown accumulation mode %d", mode);
-    return g_accum.exchange(mode);
+    const int prev = g_accum;
+    g_accum = mode;
+    return prev;
 }
 
 int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll)

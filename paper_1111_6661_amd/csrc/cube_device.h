@@ -519,6 +519,20 @@ __device__ __forceinline__ HistRange range_of_extrema(float fmn, float fmx, unsi
     return r;
 }
 
+// Moments over the extended reals.  An infinite voxel is a valid value and
+// always one of the extrema, so the exact min and max show whether any are
+// present, at no cost per voxel: +Inf alone makes the mean +Inf, -Inf alone
+// -Inf, both NaN (Inf - Inf); and since the deviation of an infinite voxel
+// from such a mean is not finite, m2 and std are NaN.  Without infinities
+// the merged finite moments stand.
+__device__ __forceinline__ void extended_real_moments(cube_stats_t &o)
+{
+    const bool pinf = o.max == INFINITY, ninf = o.min == -INFINITY;
+    if (!pinf && !ninf) return;
+    o.mean = (pinf && ninf) ? (double)qnan() : (pinf ? (double)INFINITY : -(double)INFINITY);
+    o.m2 = o.std = (double)qnan();
+}
+
 // The global stage of a stats pass: merge `n_recs` records (all threads of
 // the block call it), then thread 0 writes the result and, when `range_out`
 // is given, the [min, max] histogram range with its FP32 scale.  Returns the
@@ -558,6 +572,7 @@ __device__ void finish_stats(const WaveRec *recs, int n_recs, int accum_mode,
         o.m2 = m2 < 0.0 ? 0.0 : m2;
         o.std = accum_mode == CUBE_ACCUM_FP64MERGE ? sqrt(o.m2 / (double)nv)
                                                    : (double)sqrtf((float)o.m2 / (float)nv);
+        extended_real_moments(o);
     }
     if (range_out) {
         const HistRange r = range_of_extrema(fmn, fmx, nv, nbins);

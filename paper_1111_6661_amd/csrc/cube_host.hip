@@ -73,6 +73,7 @@ __global__ void k_merge_chunks(const cube_stats_t *chunks, int n, unsigned long 
         o.mean = mean;
         o.m2 = m2 < 0.0 ? 0.0 : m2;
         o.std = sqrt(o.m2 / (double)nv);
+        extended_real_moments(o);
     }
     if (range_out) {
         const HistRange r = range_of_extrema(mn, mx, nv, nbins);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <new>
+#include <vector>
 
 #include "cubestats.h"
 
@@ -117,6 +118,12 @@ int check_range(float lo, float hi, int32_t nbins, HistRange *r);
 void collapse(const Box &b, Geom *g);
 int cu_count();
 int accum_mode();
+// Test knobs: the values given for `kind` in the environment variable
+// CUBE_FAULT_INJECT, a comma-separated list of kind:N items in which a bare
+// N repeats the kind before it ("launch:2,5,event:3,expire:1").  Read when a
+// server or batch is created; they force failure paths from the host while
+// every kernel still runs to its normal end.
+std::vector<uint64_t> fault_inject(const char *kind);
 void get_launch(int *threads, int *blocks, int *copies, int *unroll);
 
 // The launch shape of one pass over a validated box: statistics (`stats`)

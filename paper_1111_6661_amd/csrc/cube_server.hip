@@ -16,6 +16,7 @@
 // query at a time, in arrival order, each through the single-box entry
 // point on one stream.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -54,6 +55,7 @@ struct Slot {
     hipEvent_t done = nullptr;
     std::vector<uint64_t> ids;
     bool busy = false;
+    bool inject_event_error = false;  // test knob: this launch's event reports an error
 };
 
 int64_t query_voxels(const cube_query_t &q)
@@ -91,32 +93,18 @@ struct cube_server {
     int64_t tile_voxels = 0;             // 0: each query's own automatic size
     uint64_t launches = 0;               // batches (or plain queries) launched
     std::vector<uint64_t> inject_fail;   // launch numbers that fail on purpose
+    std::vector<uint64_t> inject_event;  // launch numbers whose event reports an error
 };
 
 namespace {
 
 // Launch one batch (or one plain query) on a slot.  Called with the lock
 // held.  Returns CUBE_OK or the first error (then no work was queued).
-// CUBE_FAULT_INJECT="launch:N[,M...]": launches number N, M, ... (counted
-// from 1 per server) fail on the host before anything is queued, as a failed
-// launch would.  For tests of failure handling; no kernel is affected.
-std::vector<uint64_t> parse_fault_inject()
-{
-    std::vector<uint64_t> out;
-    const char *env = getenv("CUBE_FAULT_INJECT");
-    if (!env || strncmp(env, "launch:", 7) != 0) return out;
-    const char *p = env + 7;
-    while (*p) {
-        char *end = nullptr;
-        const unsigned long long v = strtoull(p, &end, 10);
-        if (end == p) break;
-        out.push_back((uint64_t)v);
-        p = *end == ',' ? end + 1 : end;
-        if (*end != ',') break;
-    }
-    return out;
-}
-
+// Test knobs (CUBE_FAULT_INJECT, launches counted from 1 per server):
+// "launch:N" makes launch N fail on the host before anything is queued, as
+// a failed launch would; "event:N" makes the completion event of launch N
+// report an error, as a device-side fault would (the work itself still runs
+// to its end, so no kernel is affected).
 int launch_on(cube_server *srv, Slot &sl, const std::vector<PolicyQuery> &batch)
 {
     const uint64_t nth = ++srv->launches;
@@ -124,6 +112,9 @@ int launch_on(cube_server *srv, Slot &sl, const std::vector<PolicyQuery> &batch)
         if (f == nth)
             return fail(CUBE_EDEVICE, "injected launch failure (launch %llu)",
                         (unsigned long long)nth);
+    sl.inject_event_error = false;
+    for (uint64_t f : srv->inject_event)
+        if (f == nth) sl.inject_event_error = true;
     std::vector<cube_query_t> qs;
     qs.reserve(batch.size());
     for (const PolicyQuery &p : batch) qs.push_back(srv->entries[p.id].q);
@@ -165,12 +156,15 @@ void worker_loop(cube_server *srv)
             const double t = now_s();
             // A query already completed may also have been collected (and
             // erased) by cube_server_wait: look entries up, never create.
-            if (srv->mode == 0) {
+            // Successes complete as soon as their flag is up; a failed query
+            // is reported only once its whole launch has ended (below), so
+            // its caller never frees outputs a kernel still writes.
+            if (srv->mode == 0 && !sl.inject_event_error) {
                 for (size_t k = 0; k < sl.ids.size(); ++k) {
                     auto it = srv->entries.find(sl.ids[k]);
                     if (it == srv->entries.end()) continue;
                     Entry &e = it->second;
-                    if (e.state == 1 && cube_batch_query_done(sl.batch, (int32_t)k)) {
+                    if (e.state == 1 && cube_batch_query_done(sl.batch, (int32_t)k) == 1) {
                         e.state = 2;
                         e.t_done = t;
                         srv->latencies.push_back(t - e.t_submit);
@@ -179,16 +173,51 @@ void worker_loop(cube_server *srv)
                     }
                 }
             }
-            if (hipEventQuery(sl.done) != hipSuccess) continue;
-            for (uint64_t id : sl.ids) {
-                auto it = srv->entries.find(id);
-                if (it == srv->entries.end()) continue;
-                Entry &e = it->second;
-                if (e.state == 2) continue;
-                e.state = 2;
-                e.t_done = t;
-                srv->latencies.push_back(t - e.t_submit);
-                ++srv->n_done;
+            hipError_t eq = sl.inject_event_error ? hipErrorLaunchFailure : hipEventQuery(sl.done);
+            if (eq == hipErrorNotReady) continue;
+            if (eq != hipSuccess) {
+                // The launch failed on the device: its unfinished queries fail.
+                // Wait for whatever still runs on the stream before the slot
+                // is used again (a real fault returns at once).
+                char msg[160];
+                snprintf(msg, sizeof msg, "the launch of this query failed on the device: %s (%d)",
+                         hipGetErrorString(eq), (int)eq);
+                (void)hipGetLastError();
+                lk.unlock();
+                hipStreamSynchronize(sl.stream);
+                (void)hipGetLastError();
+                lk.lock();
+                sl.inject_event_error = false;
+                for (uint64_t id : sl.ids) {
+                    auto it = srv->entries.find(id);
+                    if (it == srv->entries.end()) continue;
+                    Entry &e = it->second;
+                    if (e.state == 2) continue;
+                    e.state = 2;
+                    e.rc = CUBE_EDEVICE;
+                    e.t_done = now_s();
+                    strncpy(e.err, msg, sizeof e.err - 1);
+                    ++srv->n_failed;
+                }
+            } else {
+                for (size_t k = 0; k < sl.ids.size(); ++k) {
+                    auto it = srv->entries.find(sl.ids[k]);
+                    if (it == srv->entries.end()) continue;
+                    Entry &e = it->second;
+                    if (e.state == 2) continue;
+                    e.state = 2;
+                    e.t_done = t;
+                    // The launch has ended: a query whose flag says it failed
+                    // (its range wait expired) reports that; the others are done.
+                    if (srv->mode == 0 && cube_batch_query_done(sl.batch, (int32_t)k) < 0) {
+                        e.rc = CUBE_EDEVICE;
+                        strncpy(e.err, cube_last_error(), sizeof e.err - 1);
+                        ++srv->n_failed;
+                    } else {
+                        srv->latencies.push_back(t - e.t_submit);
+                        ++srv->n_done;
+                    }
+                }
             }
             sl.ids.clear();
             sl.busy = false;
@@ -263,7 +292,8 @@ int cube_server_create(int32_t mode, int32_t slots, int32_t max_batch, int64_t m
     srv->lim.max_batch_voxels = (int64_t)1 << 32;
     if (tile_voxels) srv->tile_voxels = tile_voxels;
     srv->policy = new Policy(srv->lim);
-    srv->inject_fail = parse_fault_inject();
+    srv->inject_fail = fault_inject("launch");
+    srv->inject_event = fault_inject("event");
     hipGetDevice(&srv->device);
     srv->slots.resize((size_t)srv->lim.slots);
     for (Slot &sl : srv->slots) {

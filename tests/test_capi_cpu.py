@@ -65,6 +65,11 @@ def test_bad_ranges_rejected_before_gpu(lo, hi, nbins, why):
 @pytest.mark.parametrize("dims,why", [
     ([-1, 4, 4, 0, 0], "negative"), ([8, 4, 4, 7, 0], "row pitch"),
     ([8, 4, 4, 8, 20], "plane pitch"), ([1 << 41, 1, 1, 0, 0], "too large"),
+    # pitches whose extent would wrap 64-bit arithmetic (the end of the box
+    # would then look like a few bytes past its start)
+    ([1, 3, 1, 3 << 61, 0], "too large"), ([1, 3, 1, (1 << 63) - 1, 0], "too large"),
+    ([1, 1, 3, 0, 3 << 61], "overflows"), ([4, 2, 3, 1 << 40, 1 << 61], "overflows"),
+    ([4, 1 << 22, 1, 1 << 41, 0], "too large"), ([1, 2, 2, 1 << 61, 0], "overflows"),
 ])
 def test_bad_shapes_rejected_before_gpu(dims, why):
     code, msg = _code(cs.cube_hist, 0x1000, dims, 0.0, 1.0, 8)
@@ -91,6 +96,24 @@ def test_mode_and_launch_setters_validate():
     prev = cs.cube_set_accum_mode(cs.CUBE_ACCUM_KAHAN32)
     assert cs.cube_set_accum_mode(prev) == cs.CUBE_ACCUM_KAHAN32
     cs.cube_set_launch(0, 0, 0, 0)
+
+
+def test_mode_is_per_thread():
+    """The precision mode set on one thread is not seen by another: a new
+    thread starts from the production mode, whatever the caller set."""
+    import threading
+    prev = cs.cube_set_accum_mode(cs.CUBE_ACCUM_NAIVE32)
+    seen = []
+    try:
+        th = threading.Thread(target=lambda: seen.append(
+            cs.cube_set_accum_mode(cs.CUBE_ACCUM_KAHAN32)))
+        th.start()
+        th.join()
+        assert seen == [cs.CUBE_ACCUM_FP64MERGE]
+        # the other thread's KAHAN32 did not reach this one
+        assert cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE) == cs.CUBE_ACCUM_NAIVE32
+    finally:
+        cs.cube_set_accum_mode(prev)
 
 
 def test_binding_has_no_cpu_fallback():

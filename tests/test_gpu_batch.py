@@ -277,3 +277,41 @@ def test_batch64_workload_precision(cs):
         cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
     print("batch64 worst std rel err:", worst)
     assert worst["batched"] <= 1e-6
+
+
+def test_expired_range_wait_fails_only_its_query(cs, monkeypatch):
+    """A two-pass query whose bounded wait for its own range gives up (forced
+    from the host: in launch 1 of this batch every range wait gives up at
+    once, and every kernel still runs to its end) completes marked as failed;
+    the other queries of the batch are unaffected; the batch's check reports
+    it once.  The next launch -- over data changed in place, so a range left
+    up by launch 1 would give wrong bins -- is whole and correct again."""
+    monkeypatch.setenv("CUBE_FAULT_INJECT", "expire:1")
+    b = cs.Batch(tile_voxels=1 << 14)
+    monkeypatch.delenv("CUBE_FAULT_INJECT")
+    items = make_items(seed=17, n=8)
+    kinds = [cs.CUBE_Q_MINMAX, cs.CUBE_Q_STATS, cs.CUBE_Q_FUSED, cs.CUBE_Q_HIST]
+    outs = Outputs(len(items), 256)
+    qs = queries_for(cs, items, outs, kinds, [256, 64])
+    b.enqueue(qs)
+    torch.cuda.synchronize()
+    for i in range(len(items)):
+        kind = kinds[i % len(kinds)]
+        if kind == cs.CUBE_Q_MINMAX:
+            with pytest.raises(cs.CubeError, match="expired"):
+                b.query_done(i)
+        else:
+            assert b.query_done(i)
+            check_query(cs, outs, i, items[i], kind, [256, 64][i % 2])
+    with pytest.raises(cs.CubeError, match="timed out"):
+        b.check()
+    b.check()                      # reported once
+    for t in items:                # new data under the same pointers
+        t.mul_(-3.0).add_(7.0)
+    outs.cnt.zero_()
+    b.relaunch()
+    b.check()
+    for i in range(len(items)):
+        assert b.query_done(i)
+        check_query(cs, outs, i, items[i], kinds[i % len(kinds)], [256, 64][i % 2])
+    b.close()

@@ -111,6 +111,13 @@ def bits(u):
     return np.array(u, dtype=np.uint32).view(np.float32)
 
 
+def _one_inf(n, at, v):
+    a = np.random.default_rng(n).standard_normal(n).astype(np.float32)
+    a[::97] = np.nan
+    a[at] = v
+    return a
+
+
 def test_edge_values(cs):
     cases = {
         "signed-zeros": np.array([0.0, -0.0, 0.0, np.nan], np.float32),
@@ -124,12 +131,28 @@ def test_edge_values(cs):
         "big-offset": (1e4 + np.random.default_rng(1).standard_normal(200_000) * 1e-3
                        ).astype(np.float32),
         "with-inf": np.array([1.0, np.inf, -2.0, np.nan, -np.inf, 3.0], np.float32),
+        "plus-inf-only": np.array([1.0, np.inf, 2.0], np.float32),
+        "minus-inf-only": np.array([np.nan, -np.inf, 1.0, -5.0], np.float32),
+        "one-inf-in-many": _one_inf(300_017, 123_457, np.inf),
+        "one-minus-inf-in-many": _one_inf(1_000_003, 999_999, -np.inf),
     }
     for name, a in cases.items():
         t = _dev(a)
         ref = oracle.stats(a)
         st = cs.stats(t)
         assert_stats_match(st, ref, name)
+        if "inf" in name:
+            # the extended-real moments on every path: stats, fused, two-pass
+            assert not math.isfinite(ref.mean) and math.isnan(ref.std), (name, ref)
+            st_f, _ = cs.stats_hist(t, -1.0, 2.0, 16)
+            assert_stats_match(st_f, ref, name + " fused")
+            out = torch.zeros(64, dtype=torch.uint8, device="cuda")
+            cs.cube_batch_run([cs.make_query(t.data_ptr(), (a.size, 1, 1), cs.CUBE_Q_STATS,
+                                             out=out.data_ptr())])
+            st_b = cs.Stats.from_bytes(out.cpu().numpy().tobytes())
+            assert_stats_match(st_b, ref, name + " batched")
+            st_h, _ = cs.host_query(a, cs.CUBE_Q_STATS, chunk_voxels=4096)
+            assert_stats_match(st_h, ref, name + " out-of-core")
         if name == "subnormal":   # deviations ~1e-39: below the FP32 moment range
             from tests.parity import moments_in_fp32_range
             assert not moments_in_fp32_range(ref)

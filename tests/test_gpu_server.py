@@ -92,10 +92,11 @@ def test_server_mix_equals_alone(cs, cubes, tile):
             assert torch.equal(o1, out[i]), f"query {i} stats differ alone vs in the mix"
         if kind != cs.CUBE_Q_STATS:
             assert torch.equal(c1, cnt[i, :nb + 3]), f"query {i} counts differ"
-    # and a sample agrees with the oracle
-    for i in range(0, len(specs), 7):
+    # and every served query agrees with the oracle
+    hosts = [t.cpu().numpy() for t in cubes]
+    for i in range(len(specs)):
         q, c, sl, kind, nb, lo, hi = specs[i]
-        host = cubes[c].cpu().numpy()[sl]
+        host = hosts[c][sl]
         ref = oracle.stats(host)
         if kind != cs.CUBE_Q_HIST:
             st = cs.Stats.from_bytes(out[i].cpu().numpy().tobytes())
@@ -189,3 +190,76 @@ def test_injected_launch_failure_is_isolated(cs, monkeypatch):
     torch.cuda.synchronize()
     for i in (0, 2, 4, 5):
         assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref, f"query {i}")
+
+
+def test_injected_event_error_is_isolated(cs, monkeypatch):
+    """A launch whose completion event reports a device error (forced from
+    the host for launch 2: the work itself runs to its end) fails the
+    queries of that launch with the error; the slot is freed, the server
+    goes on serving, and destroying it returns."""
+    monkeypatch.setenv("CUBE_FAULT_INJECT", "event:2")
+    t = torch.randn(1 << 16, device="cuda")
+    ref = oracle.stats(t.cpu().numpy())
+    out = torch.zeros((5, 64), dtype=torch.uint8, device="cuda")
+    for mode in (cs.CUBE_SERVE_BATCHED, cs.CUBE_SERVE_PLAIN):
+        out.zero_()
+        srv = cs.Server(mode, slots=1, max_batch=1)
+        results = []
+        for i in range(5):
+            qid = srv.submit(cs.make_query(*cs.box_of(t), cs.CUBE_Q_STATS, 0, 0.0, 0.0,
+                                           out[i].data_ptr()))
+            try:
+                srv.wait(qid, timeout_s=60)
+                results.append("ok")
+            except cs.CubeError as e:
+                assert "failed on the device" in str(e)
+                results.append("failed")
+        assert results == ["ok", "failed", "ok", "ok", "ok"], (mode, results)
+        _, _, n = srv.latency()
+        assert n == 4
+        srv.close()
+        torch.cuda.synchronize()
+        for i in (0, 2, 3, 4):
+            assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref, f"q{i}")
+    monkeypatch.delenv("CUBE_FAULT_INJECT")
+
+
+def test_expired_range_wait_fails_only_its_query_served(cs, cubes, monkeypatch):
+    """In the first launch of each slot every range wait gives up at once
+    (forced from the host; every kernel still ends normally): exactly the
+    two-pass queries of those launches fail, every other query is served
+    correctly, later launches of the same slots are whole, and destroying
+    the server returns."""
+    monkeypatch.setenv("CUBE_FAULT_INJECT", "expire:1")
+    srv = cs.Server(cs.CUBE_SERVE_BATCHED, slots=2, max_batch=6)
+    monkeypatch.delenv("CUBE_FAULT_INJECT")
+    specs, out, cnt = random_queries(cs, cubes, 24, seed=9, nbins_max=1024)
+    # the first query opens the first launch: make it a two-pass one
+    q, c, sl, kind, nb, lo, hi = specs[0]
+    q.kind = cs.CUBE_Q_MINMAX
+    specs[0] = (q, c, sl, cs.CUBE_Q_MINMAX, nb, lo, hi)
+    ids = [srv.submit(s[0]) for s in specs]
+    failed = set()
+    for i, qid in enumerate(ids):
+        try:
+            srv.wait(qid, timeout_s=60)
+        except cs.CubeError as e:
+            assert "expired" in str(e), str(e)
+            failed.add(i)
+    srv.close()
+    torch.cuda.synchronize()
+    assert 0 in failed
+    assert all(specs[i][3] == cs.CUBE_Q_MINMAX for i in failed)
+    hosts = [t.cpu().numpy() for t in cubes]
+    for i, (q, c, sl, kind, nb, lo, hi) in enumerate(specs):
+        if i in failed:
+            continue
+        host = hosts[c][sl]
+        ref = oracle.stats(host)
+        if kind != cs.CUBE_Q_HIST:
+            assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref, f"q{i}")
+        got = cnt[i, :nb + 3].cpu().numpy().view(np.uint64)
+        if kind in (cs.CUBE_Q_HIST, cs.CUBE_Q_FUSED):
+            assert_counts_match(got, oracle.hist(host, lo, hi, nb), f"q{i}")
+        elif kind == cs.CUBE_Q_MINMAX and ref.n_valid:
+            assert_counts_match(got, oracle.hist(host, ref.min, ref.max, nb), f"q{i}")
