@@ -159,6 +159,26 @@ CUBE_API int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims,
                                  uint64_t *dev_counts, void *stream);
 
 /*
+ * Allocation-free form of cube_stats_hist_async, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops
+ * and harnesses that forbid hipMalloc.  Same arguments, results and errors
+ * as cube_stats_hist_async (DEVICE outputs, stream-ordered on `stream`,
+ * NULL = the default stream), with the same kernel; it makes no device or
+ * host allocation.  Its scratch (wave records, the ticket, the histogram
+ * accumulators: about 1.5 MiB) is one static device array per device, held
+ * from the first call until the process ends and cleared by a small fill
+ * kernel at every call.  Calls that overlap on one device (different
+ * streams, or threads without ordering) race on that array and must not be
+ * made.  The launch grid is narrowed to CUBE_NOALLOC_MAX_RECORDS wave
+ * records (1024 blocks of 1024 threads); an explicit cube_set_launch shape
+ * needing more is rejected with CUBE_EINVAL.
+ */
+#define CUBE_NOALLOC_MAX_RECORDS 16384
+CUBE_API int cube_stats_hist_noalloc(const float *ptr, const int64_t *dims, float lo, float hi,
+                                     int32_t nbins, cube_stats_t *dev_out,
+                                     uint64_t *dev_counts, void *stream);
+
+/*
  * Precision mode of the moments for later single-box calls from the CALLING
  * THREAD only (each thread starts with CUBE_ACCUM_FP64MERGE; other threads,
  * batches and the server are unaffected: batched and served queries always

@@ -100,6 +100,7 @@ def load() -> C.CDLL:
     lib.cube_hist_async.argtypes = [P, I64P, f32, f32, i32, P, P]
     lib.cube_stats_hist_async.argtypes = [P, I64P, f32, f32, i32, P, P, P]
     lib.cube_stats_hist_minmax_async.argtypes = [P, I64P, i32, P, P, P]
+    lib.cube_stats_hist_noalloc.argtypes = [P, I64P, f32, f32, i32, P, P, P]
     lib.cube_set_accum_mode.argtypes = [i32]
     lib.cube_set_launch.argtypes = [i32, i32, i32, i32]
     lib.cube_shutdown.restype = None
@@ -150,7 +151,8 @@ def load() -> C.CDLL:
         getattr(lib, name).restype = C.c_int
     for name in ("cube_stats", "cube_hist", "cube_stats_hist", "cube_stats_hist_minmax",
                  "cube_stats_async", "cube_hist_async", "cube_stats_hist_async",
-                 "cube_stats_hist_minmax_async", "cube_set_accum_mode", "cube_set_launch"):
+                 "cube_stats_hist_minmax_async", "cube_stats_hist_noalloc",
+                 "cube_set_accum_mode", "cube_set_launch"):
         getattr(lib, name).restype = C.c_int
     if lib.cube_abi_version() != 1:
         raise RuntimeError("libcubestats ABI version mismatch")
@@ -226,6 +228,17 @@ def cube_stats_hist_minmax_async(ptr: int, dims, nbins: int, dev_out: int, dev_c
     _check(load().cube_stats_hist_minmax_async(C.c_void_p(ptr), _dims(dims), nbins,
                                                C.c_void_p(dev_out), C.c_void_p(dev_counts),
                                                C.c_void_p(stream)))
+
+
+CUBE_NOALLOC_MAX_RECORDS = 16384
+
+
+def cube_stats_hist_noalloc(ptr: int, dims, lo: float, hi: float, nbins: int, dev_out: int,
+                            dev_counts: int, stream: int = 0) -> None:
+    """The allocation-free fused call (device outputs, stream-ordered)."""
+    _check(load().cube_stats_hist_noalloc(C.c_void_p(ptr), _dims(dims), lo, hi, nbins,
+                                          C.c_void_p(dev_out), C.c_void_p(dev_counts),
+                                          C.c_void_p(stream)))
 
 
 def cube_set_accum_mode(mode: int) -> int:

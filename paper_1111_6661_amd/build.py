@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcubestats.so")
 SOURCES = ["cube_kernels.hip", "cube_capi.hip", "cube_batch.hip", "cube_server.hip",
            "cube_tune.hip", "cube_select.hip", "cube_host.hip", "cube_project.hip", "cube_probe.hip",
-           "cube_quantile.hip"]
+           "cube_quantile.hip", "cube_noalloc.hip"]
 
 # -packed-fp32-ops: no packed FP32 instructions are emitted (the kernels are
 # written for scalar FP32 VALU operations only).  -ffp-contract=off: no

@@ -402,8 +402,12 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
     if (blocks > MAX_BLOCKS) blocks = MAX_BLOCKS;
     if ((size_t)blocks * (threads / 64) > REC_CAP) blocks = (long long)(REC_CAP / (threads / 64));
     p->blocks = (int)blocks;
+    cut_rows(p->g, blocks);
+    return CUBE_OK;
+}
 
-    Geom &g = p->g;
+void cut_rows(Geom &g, long long blocks)
+{
     const long long rows = g.ny * g.nz;
     long long segs = 1;
     if (rows < blocks) segs = (blocks + rows - 1) / rows;
@@ -414,7 +418,6 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
     g.seg_len = seg_len;
     g.segs = segs;
     g.n_units = rows * segs;
-    return CUBE_OK;
 }
 
 __global__ void k_write_empty(cube_stats_t *out, unsigned long long *counts, int nbins)

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <new>
+#include <string>
 #include <vector>
 
 #include "cubestats.h"
@@ -107,6 +108,7 @@ struct Plan {
     }
 
 // Set the calling thread's error text and return `code`.
+extern thread_local std::string g_err;
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 // Host-only checks of a box (no HIP call) and the checks that need HIP.
@@ -130,6 +132,9 @@ void get_launch(int *threads, int *blocks, int *copies, int *unroll);
 // and/or a histogram (hist_kind_req 1) of nbins bins; the explicit shape of
 // cube_set_launch, else the tuned one, else the default rules.
 int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p);
+// Cut the rows of a collapsed box into segments so that there are at least
+// `blocks` work units (a row is never cut below 4 floats).
+void cut_rows(Geom &g, long long blocks);
 
 // One pass over a validated device box on stream `s`, with the calling
 // stream's workspace: statistics (to dev_out) and/or a histogram (HIST_NONE

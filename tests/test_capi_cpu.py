@@ -86,6 +86,15 @@ def test_bad_pointers_rejected_before_gpu():
     assert lib.cube_stats_hist(C.c_void_p(0x1000), d, 0.0, 1.0, 8, None, None) == cs.CUBE_EINVAL
     assert lib.cube_hist(C.c_void_p(0x1000), None, 0.0, 1.0, 8, None) == cs.CUBE_EINVAL
     assert lib.cube_stats_async(C.c_void_p(0x1000), d, None, None) == cs.CUBE_EINVAL
+    # the allocation-free call checks its arguments before any HIP call too
+    assert lib.cube_stats_hist_noalloc(C.c_void_p(0x1000), d, 0.0, 1.0, 8, None, None,
+                                       None) == cs.CUBE_EINVAL
+    code, msg = _code(cs.cube_stats_hist_noalloc, 0x1002, [4, 4, 4, 0, 0], 0.0, 1.0, 8, 0x2000,
+                      0x3000)
+    assert code == cs.CUBE_EINVAL and "aligned" in msg
+    code, msg = _code(cs.cube_stats_hist_noalloc, 0x1000, [4, 4, 4, 0, 0], 1.0, 0.0, 8, 0x2000,
+                      0x3000)
+    assert code == cs.CUBE_EINVAL and "hi < lo" in msg
 
 
 def test_mode_and_launch_setters_validate():
