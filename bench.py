@@ -40,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MIN_SERVE_QUERIES = 10_000
 
 
 def log(msg: str) -> None:
@@ -207,11 +208,34 @@ def bench_batch64(cs, synth, torch, dev, steps: int):
             "max_std_rel_diff_batched_vs_plain": worst}
 
 
+STRESS_ORACLE = "tests/golden/stress128g_oracle.json"
+
+
+def stress_oracle_reference(synth):
+    """The oracle's statistics of the whole stress cube, as stored by
+    tests/golden/make_stress128g_oracle.py (read as data; the oracle is not
+    run here), or None when the file is missing or was written for another
+    generator or seed."""
+    import hashlib
+    path = os.path.join(ROOT, STRESS_ORACLE)
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("synth/__init__.py", "synth/gen.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if g.get("generator_sha256_16") != h.hexdigest()[:16] or g.get("seed") != synth.BASE_SEED + 4:
+        return None
+    return g["stats"]
+
+
 def bench_stress(cs, synth, torch, dev, steps: int, tune: bool = False):
     """The precision-stress cube at full size (4096 x 4096 x 2048, 128 GiB,
     offset 1e4): fused pass throughput over [min, max] with 4096 bins, and
-    the moments of the three accumulation modes side by side (the oracle
-    comparison of these modes runs in the test suite at 16 GiB)."""
+    the moments of the three accumulation modes side by side, with their
+    errors relative to the oracle's values for the whole cube (stored with
+    the tests; the test suite recomputes them live)."""
     name = "stress128g"
     r = synth.WORKLOADS[name]
     nb = synth.HIST_BINS[name]
@@ -240,9 +264,18 @@ def bench_stress(cs, synth, torch, dev, steps: int, tune: bool = False):
                           stream, steps, 2)
     c = cnt.cpu().numpy()
     ref = modes["fp64merge"]
+    orc = stress_oracle_reference(synth)
+    vs_oracle = None
+    if orc is not None and orc["n_valid"] == st.n_valid and orc["min"] == st.min \
+            and orc["max"] == st.max:
+        vs_oracle = {k: {"mean": abs(v["mean"] - orc["mean"]) / abs(orc["mean"]),
+                         "std": abs(v["std"] - orc["std"]) / orc["std"]}
+                     for k, v in modes.items()}
     del cube
     torch.cuda.empty_cache()
     return {"voxels": r.n, "nbins": nb, "fused_ms": ms, "voxels_per_s": r.n / (ms * 1e-3),
+            "rel_err_vs_oracle": vs_oracle,
+            "oracle_reference": STRESS_ORACLE if vs_oracle is not None else None,
             "autotune": tuned,
             "pct_hbm_peak": 100.0 * 4 * r.n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bin0_fraction_of_valid": float(c[0]) / max(1, st.n_valid),
@@ -315,20 +348,24 @@ def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7,
                                        cs.CUBE_Q_STATS, cs.CUBE_Q_FUSED)
     cap, _, _ = replay(cs.CUBE_SERVE_PLAIN, cap_specs, open_loop=False)
     qps = load_frac * cap["qps"]
-    n = max(50, int(qps * seconds))
+    # at least 10^4 queries, so that p99 rests on about 100 samples above it
+    n = max(MIN_SERVE_QUERIES, int(qps * seconds))
     specs = workloads.query_stream(shapes, ranges, n, qps, synth.BASE_SEED + 31,
                                    cs.CUBE_Q_STATS, cs.CUBE_Q_FUSED)
     log(f"serve: plain capacity {cap['qps']:.0f} QPS; replaying {n} queries at {qps:.0f} QPS")
     plain, po, pc = replay(cs.CUBE_SERVE_PLAIN, specs, open_loop=True)
     served, so, sc = replay(cs.CUBE_SERVE_BATCHED, specs, open_loop=True)
-    # the same stream served with one fixed 2^20-voxel tile for every query
-    fixed, fo, fc = replay(cs.CUBE_SERVE_BATCHED, specs, open_loop=True, tile=1 << 20)
-    same_counts = bool(torch.equal(pc, sc)) and bool(torch.equal(pc, fc))
+    # the first quarter of the same stream served with one fixed 2^20-voxel
+    # tile for every query
+    nf = max(50, n // 4)
+    fixed, fo, fc = replay(cs.CUBE_SERVE_BATCHED, specs[:nf], open_loop=True, tile=1 << 20)
+    same_counts = bool(torch.equal(pc, sc)) and bool(torch.equal(pc[:nf], fc))
     same_extrema = True
+    po, so, fo = po.cpu(), so.cpu(), fo.cpu()
     for i in range(n):
-        a = cs.Stats.from_bytes(po[i].cpu().numpy().tobytes())
-        for o in (so, fo):
-            b = cs.Stats.from_bytes(o[i].cpu().numpy().tobytes())
+        a = cs.Stats.from_bytes(po[i].numpy().tobytes())
+        for o in ((so, fo) if i < nf else (so,)):
+            b = cs.Stats.from_bytes(o[i].numpy().tobytes())
             if a.n_valid != b.n_valid or a.n_nan != b.n_nan or \
                     not (a.min == b.min or a.min != a.min) or not (a.max == b.max or a.max != a.max):
                 same_extrema = False
@@ -348,7 +385,8 @@ def bench_serve(cs, synth, torch, dev, seconds: float, load_frac: float = 0.7,
     torch.cuda.empty_cache()
     return {"cubes": len(recipes), "resident_gib": sum(r.n for r in recipes) * 4 / 2**30,
             "plain_capacity_qps": cap["qps"], "offered_qps": qps, "load_frac": load_frac,
-            "queries": n, "plain": plain, "served": served, "served_fixed_tile_2e20": fixed,
+            "queries": n, "plain": plain, "served": served,
+            "served_fixed_tile_2e20": dict(fixed, note=f"first {nf} queries of the stream"),
             "p50_speedup": plain["p50_ms"] / served["p50_ms"],
             "p99_speedup": plain["p99_ms"] / served["p99_ms"],
             "load_sweep": loads,
@@ -376,11 +414,13 @@ def bench_select(cs, torch, cube, n_valid: int, reps: int):
     for _ in range(reps):
         m, nv = cs.median(cube)
     med_ms = (time.perf_counter() - t0) * 1e3 / reps
-    # quantiles: the quartiles, and 64 levels at once (three reads each)
-    qtimes = {}
+    # quantiles: the quartiles, and 64 levels at once (three or four reads
+    # each, as the call's plan took them)
+    qtimes, qreads = {}, {}
     for label, lv in (("quartiles", [0.25, 0.5, 0.75]),
                       ("levels64", [i / 63 for i in range(64)])):
         cs.quantiles(cube, lv)
+        qreads[label] = cs.cube_last_quantile_reads()
         t0 = time.perf_counter()
         for _ in range(reps):
             qv, _ = cs.quantiles(cube, lv)
@@ -393,8 +433,9 @@ def bench_select(cs, torch, cube, n_valid: int, reps: int):
             "select_ms": round(sel_ms, 4), "median_ms": round(med_ms, 4),
             "select_gbs_2_passes": 2 * 4 * n / (sel_ms * 1e-3) / 1e9,
             "quantiles_ms": qtimes,
-            "quantiles_gbs_3_passes": {kq: 3 * 4 * n / (v_ * 1e-3) / 1e9
-                                       for kq, v_ in qtimes.items()},
+            "quantiles_reads": qreads,
+            "quantiles_gbs": {kq: qreads[kq] * 4 * n / (v_ * 1e-3) / 1e9
+                              for kq, v_ in qtimes.items()},
             "rank_property_holds": below <= k < at_or_below and nv == n_valid}
 
 
@@ -479,7 +520,8 @@ def main() -> int:
     ap.add_argument("--no-stress", action="store_true", help="skip the 128 GiB stress cube")
     ap.add_argument("--no-select", action="store_true", help="skip selection and median")
     ap.add_argument("--no-host", action="store_true", help="skip the out-of-core host queries")
-    ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the replayed query stream (at least 10^4 queries)")
     ap.add_argument("--serve-sweep", default="",
                     help="more offered loads (fractions of the plain capacity), e.g. 0.5,0.9")
     args = ap.parse_args()
@@ -672,6 +714,12 @@ def main() -> int:
             f"{sv['served_fixed_tile_2e20']['p99_ms']:.2f} ms")
     if args.tune_save:
         cs.cube_tune_save(args.tune_save)
+    # release everything before the line is printed: no device or pinned
+    # memory, stream or library thread outlives the measurement
+    cube = None
+    torch.cuda.synchronize()
+    cs.cube_shutdown()
+    torch.cuda.empty_cache()
     print(json.dumps(result), flush=True)
     return 0 if all(parity.values()) else 1
 

@@ -244,6 +244,13 @@ CUBE_API int cube_quantiles(const float *ptr, const int64_t *dims, const double 
                             double *out, uint64_t *n_valid);
 
 /*
+ * Number of reads of the box (3 or 4, see cube_quantiles) that the CALLING
+ * THREAD's last successful cube_quantiles call made, for measuring its bytes
+ * moved; 0 before the thread's first successful call.  Never fails.
+ */
+CUBE_API int cube_last_quantile_reads(void);
+
+/*
  * Projections along the channel axis z: the maps a viewer of spectral cubes
  * shows beside the rendered volume (Section 2).  For every spatial pixel
  * (x, y) of the box, over its nz channels:

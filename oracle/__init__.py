@@ -98,6 +98,8 @@ class Oracle:
         lib.oracle_sweep2.restype = C.c_int
         lib.oracle_finish.argtypes = [C.POINTER(_Sweep1), C.POINTER(_Sweep2),
                                       C.POINTER(_Stats)]
+        lib.oracle_sweep1_add.argtypes = [C.POINTER(_Sweep1), C.POINTER(_Sweep1)]
+        lib.oracle_sweep2_add.argtypes = [C.POINTER(_Sweep2), C.POINTER(_Sweep2)]
         lib.oracle_stats.argtypes = [P, i64, i64, i64, i64, i64, C.POINTER(_Stats)]
         lib.oracle_stats.restype = C.c_int
         lib.oracle_hist_scale.argtypes = [f32, f32, C.c_int32, C.POINTER(f32)]
@@ -145,6 +147,52 @@ class Oracle:
         for a in pieces():
             if lib.oracle_sweep2(C.byref(s2), *box_of(a), mean) != 0:
                 raise ValueError("invalid box")
+        lib.oracle_finish(C.byref(s1), C.byref(s2), C.byref(out))
+        return Stats(*(getattr(out, f[0]) for f in _Stats._fields_))
+
+    def stats_slabs(self, slabs, threads: int) -> Stats:
+        """Statistics of a cube given as consecutive slabs, swept side by side.
+
+        ``slabs`` is a list of callables, one per slab in cube order, each
+        returning an iterator of float32 arrays (the slab's pieces, as for
+        ``stats_pieces``); each is called twice.  Every slab is swept into a
+        record of its own on one of ``threads`` host threads (the C sweeps
+        release the GIL), and the records are added in slab order, so the
+        result is that of one sweep over the whole cube up to the rounding
+        of the compensated sums.
+        """
+        from concurrent.futures import ThreadPoolExecutor
+        lib = self.lib
+
+        def sweep1(pieces):
+            s = _Sweep1()
+            lib.oracle_sweep1_init(C.byref(s))
+            for a in pieces():
+                if lib.oracle_sweep1(C.byref(s), *box_of(a)) != 0:
+                    raise ValueError("invalid box")
+            return s
+
+        with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+            r1 = list(ex.map(sweep1, slabs))
+            s1 = _Sweep1()
+            lib.oracle_sweep1_init(C.byref(s1))
+            for r in r1:
+                lib.oracle_sweep1_add(C.byref(s1), C.byref(r))
+            mean = lib.oracle_sweep1_mean(C.byref(s1))
+
+            def sweep2(pieces):
+                s = _Sweep2()
+                lib.oracle_sweep2_init(C.byref(s))
+                for a in pieces():
+                    if lib.oracle_sweep2(C.byref(s), *box_of(a), mean) != 0:
+                        raise ValueError("invalid box")
+                return s
+
+            r2 = list(ex.map(sweep2, slabs))
+        s2, out = _Sweep2(), _Stats()
+        lib.oracle_sweep2_init(C.byref(s2))
+        for r in r2:
+            lib.oracle_sweep2_add(C.byref(s2), C.byref(r))
         lib.oracle_finish(C.byref(s1), C.byref(s2), C.byref(out))
         return Stats(*(getattr(out, f[0]) for f in _Stats._fields_))
 
@@ -236,6 +284,10 @@ def stats(a):
 
 def stats_pieces(pieces):
     return default().stats_pieces(pieces)
+
+
+def stats_slabs(slabs, threads):
+    return default().stats_slabs(slabs, threads)
 
 
 def hist_scale(lo, hi, nbins):

@@ -73,6 +73,8 @@
  * Every entry point can be called repeatedly on pieces of a cube ("chunk
  * streaming") so that a cube larger than host memory can be checked piece by
  * piece: sweep 1 over all pieces, then sweep 2 over all pieces, then finish.
+ * The sweep records of separate slabs can also be added together in slab
+ * order (oracle_sweep*_add), so that slabs are swept on several threads.
  */
 #include <math.h>
 #include <stdint.h>
@@ -207,6 +209,44 @@ int oracle_sweep2(oracle_sweep2_t *s, const float *p, int64_t nx, int64_t ny,
                 neumaier_add(&s->sq, &s->sq_c, d * d);
             }
     return 0;
+}
+
+/*
+ * Sweep records of consecutive slabs of one cube, added together: a sweep
+ * over slab A then slab B in one record equals the record of A with the
+ * record of B added by these functions (counts add, extrema by the same
+ * order, each compensated sum adds the other's pair).  They let slabs be
+ * swept side by side on several host threads and combined in slab order.
+ */
+void oracle_sweep1_add(oracle_sweep1_t *a, const oracle_sweep1_t *b)
+{
+    if (b->n_valid) {
+        if (a->n_valid == 0) {
+            a->min = b->min;
+            a->max = b->max;
+        } else {
+            if (before(b->min, a->min)) a->min = b->min;
+            if (before(a->max, b->max)) a->max = b->max;
+        }
+    }
+    a->n_total += b->n_total;
+    a->n_valid += b->n_valid;
+    a->n_nan += b->n_nan;
+    neumaier_add(&a->sum, &a->sum_c, b->sum);
+    a->sum_c += b->sum_c;
+    neumaier_add(&a->sabs, &a->sabs_c, b->sabs);
+    a->sabs_c += b->sabs_c;
+    a->n_pinf += b->n_pinf;
+    a->n_ninf += b->n_ninf;
+}
+
+void oracle_sweep2_add(oracle_sweep2_t *a, const oracle_sweep2_t *b)
+{
+    a->n += b->n;
+    neumaier_add(&a->dev, &a->dev_c, b->dev);
+    a->dev_c += b->dev_c;
+    neumaier_add(&a->sq, &a->sq_c, b->sq);
+    a->sq_c += b->sq_c;
 }
 
 void oracle_finish(const oracle_sweep1_t *a, const oracle_sweep2_t *b,

@@ -132,6 +132,8 @@ def load() -> C.CDLL:
     lib.cube_median.restype = C.c_int
     lib.cube_quantiles.argtypes = [P, I64P, P, i32, P, C.POINTER(C.c_uint64)]
     lib.cube_quantiles.restype = C.c_int
+    lib.cube_last_quantile_reads.argtypes = []
+    lib.cube_last_quantile_reads.restype = C.c_int
     lib.cube_autotune.argtypes = [P, I64P, i32, f32, f32, i32, i32, C.c_char_p, C.c_size_t]
     lib.cube_autotune.restype = C.c_int
     lib.cube_tune_save.argtypes = [C.c_char_p]
@@ -279,6 +281,11 @@ def cube_quantiles(ptr: int, dims, q):
 def quantiles(t, q):
     ptr, d = box_of(t)
     return cube_quantiles(ptr, d, q)
+
+
+def cube_last_quantile_reads() -> int:
+    """Reads of the box made by this thread's last successful quantiles call."""
+    return int(load().cube_last_quantile_reads())
 
 
 def select(t, rank: int) -> float:

@@ -36,6 +36,10 @@
 
 namespace cube {
 
+// Reads of the box made by the calling thread's last successful
+// cube_quantiles call.
+thread_local int g_quant_reads = 0;
+
 namespace {
 
 constexpr int Q_THREADS = 1024;
@@ -230,8 +234,10 @@ struct GpuPasses {
     QuantWorkspace *w;
     Geom g;
     int blocks;
+    int reads = 0;  // reads of the box so far
     int first(const unsigned long long **counts, unsigned long long *n)
     {
+        ++reads;
         const int rc = quant_pass(w, g, blocks, 0, 20, 12, 0, 0, 1, 0, 0);
         if (rc) return rc;
         *counts = w->h_acc;
@@ -241,6 +247,7 @@ struct GpuPasses {
     // The tables are already staged in w->h_tab, which quant_pass uploads.
     int refine(const QuantPassSpec &s, const unsigned char *, const unsigned long long **counts)
     {
+        ++reads;
         const int rc = quant_pass(w, g, blocks, s.nl, s.shift, s.width, s.w2, s.w3, s.slots,
                                   s.t2_bytes, s.t3_bytes);
         if (rc) return rc;
@@ -260,6 +267,7 @@ int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t 
     scan_geom(box, P.blocks, &P.g);
     rc = quantiles_run(P, q, m, out, n_valid_out, w->h_tab, 1);
     if (rc == 1) return fail(CUBE_EINVAL, "no valid voxel");
+    if (rc == CUBE_OK) g_quant_reads = P.reads;
     return rc;
 }
 
@@ -308,5 +316,7 @@ int cube_quantiles(const float *ptr, const int64_t *dims, const double *q, int32
     return run_quantiles(b, q, m, out, n_valid);
     CUBE_GUARD_END
 }
+
+int cube_last_quantile_reads(void) { return g_quant_reads; }
 
 }  // extern "C"

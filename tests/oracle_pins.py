@@ -168,6 +168,46 @@ def pin_infinite_moments(o):
     assert t.mean == np.inf and math.isnan(t.std) and t.n_valid == b.size
 
 
+def pin_slabs(o):
+    """Slabs swept on several threads and added in slab order: counts and
+    extrema equal numpy's over the whole cube exactly, and the moments equal
+    exact rational arithmetic (``fractions``) to double rounding, including
+    a first slab with no valid voxel, signed zeros at the far end, and a sum
+    whose value survives only in the compensation of one slab (2^60 and
+    many ones, cancelled by -2^60 in the next slab)."""
+    rng = np.random.default_rng(21)
+    a = (rng.standard_normal((23, 9, 11)) * 2.5 + 4.0).astype(np.float32)
+    a[rng.random(a.shape) < 0.04] = np.nan
+    a[:3] = np.nan                       # the first slab holds no valid voxel
+    a[-1, 0, :4] = [-0.0, 0.0, -0.0, 0.0]
+    cuts = [0, 3, 4, 11, 17, 23]
+    slabs = [(lambda z0=z0, z1=z1: iter((a[z0:z1],))) for z0, z1 in zip(cuts, cuts[1:])]
+    s = o.stats_slabs(slabs, 3)
+    v = a[~np.isnan(a)].astype(np.float64)
+    assert s.n_total == a.size and s.n_valid == v.size and s.n_nan == a.size - v.size
+    assert s.min == np.nanmin(a) and s.max == np.nanmax(a)
+    fr = [Fraction(float(x)) for x in v]
+    mean = sum(fr) / len(fr)
+    m2 = sum((x - mean) ** 2 for x in fr)
+    assert abs(s.mean - float(mean)) <= 1e-15 * abs(float(mean))
+    assert abs(s.m2 - float(m2)) <= 1e-13 * float(m2)
+    one = o.stats(a)
+    assert (one.n_valid, one.min, one.max) == (s.n_valid, s.min, s.max)
+    # a sum carried by one slab's compensation term
+    big = np.float32(2.0 ** 60)
+    b = np.ones(4001, dtype=np.float32)
+    b[0], b[2000] = big, -big
+    t = o.stats_slabs([lambda: iter((b[:2000],)), lambda: iter((b[2000:],))], 2)
+    want = Fraction(3999, 4001)          # 3999 ones over 4001 valid voxels
+    assert abs(t.mean - float(want)) <= 1e-15, t.mean
+    # +Inf in the middle slab only: the extended-real reading survives the adds
+    c = rng.standard_normal(300).astype(np.float32)
+    c[150] = np.inf
+    u = o.stats_slabs([lambda: iter((c[:100],)), lambda: iter((c[100:200],)),
+                       lambda: iter((c[200:],))], 2)
+    assert u.mean == np.inf and math.isnan(u.std) and u.max == np.inf
+
+
 # ------------------------------------------------------------ extrema / NaN
 def pin_extrema_nan(o):
     rng = np.random.default_rng(3)
@@ -512,6 +552,7 @@ def pin_project(o):
 
 
 ALL_PINS = [pin_textbook, pin_exact_rational, pin_closed_forms, pin_merge, pin_infinite_moments,
+            pin_slabs,
             pin_extrema_nan, pin_strided, pin_hist_ramp, pin_hist_unit_scale,
             pin_hist_edges, pin_hist_subnormal, pin_hist_rounding_model, pin_hist_numpy,
             pin_hist_invariants, pin_hist_validation, pin_select, pin_quantiles,

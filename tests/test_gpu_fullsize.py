@@ -5,8 +5,9 @@ where the FP32-only accumulation modes are reported beside the production
 FP64-merge path; the full 128 GiB stress cube, by properties, sampled
 sub-boxes and ranks; and the serving set at its real size (about 201 GiB).
 
-The oracle runs single-threaded on host copies; these tests take a minute or
-two each and are marked `slow` as well as `gpu`.
+The oracle runs on host copies (the 128 GiB cube slab by slab on host
+threads); these tests take a minute or two each and are marked `slow` as well
+as `gpu`.
 """
 import os
 import time
@@ -15,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.devstream import host_threads, oracle_stats_of_device
 from tests.parity import assert_counts_match, assert_stats_match, rel_err
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -142,10 +144,13 @@ def test_precision_stress_16g(cs):
 @pytest.mark.timeout(900)
 def test_stress128g_full_size(cs):
     """The 128 GiB stress cube (2^35 voxels) in the launch configuration the
-    benchmark times: properties that hold at any size on the whole cube,
-    sub-boxes at the start, the middle and the far end (element offsets past
-    2^34) against the oracle, and selection, median and quantiles checked by
-    their ranks (counted on the GPU, a chunk of planes at a time)."""
+    benchmark times: properties that hold at any size on the whole cube; the
+    whole cube's statistics against the oracle (streamed to host threads),
+    for the stats, fused and two-pass calls, with the oracle-relative errors
+    of the three accumulation modes; sub-boxes at the start, the middle and
+    the far end (element offsets past 2^34) against the oracle; and
+    selection, median and quantiles checked by their ranks (counted on the
+    GPU, a chunk of planes at a time)."""
     import synth
     r = synth.WORKLOADS["stress128g"]
     nb = synth.HIST_BINS["stress128g"]
@@ -161,6 +166,45 @@ def test_stress128g_full_size(cs):
     for s in (st_f, st_2):
         assert s.min == st.min and s.max == st.max and s.n_valid == st.n_valid
         assert abs(s.mean - st.mean) <= 1e-9 * abs(st.mean) and abs(s.std - st.std) <= 1e-6 * st.std
+
+    # the whole cube against the oracle (streamed slab by slab to host
+    # threads): the production path under the tolerance rule, and the
+    # FP32-only modes reported beside it, relative to the oracle
+    t0 = time.perf_counter()
+    ref = oracle_stats_of_device(oracle, t)
+    t_oracle = time.perf_counter() - t0
+    assert_stats_match(st, ref, "stats, whole stress cube")
+    assert_stats_match(st_f, ref, "fused, whole stress cube")
+    assert_stats_match(st_2, ref, "two-pass, whole stress cube")
+    modes = {}
+    try:
+        for mode, name in ((cs.CUBE_ACCUM_NAIVE32, "naive32"), (cs.CUBE_ACCUM_KAHAN32, "kahan32"),
+                           (cs.CUBE_ACCUM_FP64MERGE, "fp64merge")):
+            cs.cube_set_accum_mode(mode)
+            modes[name] = rel_err(cs.stats(t), ref)
+    finally:
+        cs.cube_set_accum_mode(cs.CUBE_ACCUM_FP64MERGE)
+    print(f"stress128g whole cube vs oracle ({t_oracle:.0f} s of oracle on "
+          f"{host_threads()} threads), (mean err, std err): {modes}")
+    assert modes["fp64merge"][0] <= 1e-6 and modes["fp64merge"][1] <= 1e-6
+    assert modes["naive32"][1] > modes["fp64merge"][1]
+    out = os.environ.get("CUBE_PRECISION_REPORT")
+    if out:
+        import json
+        with open(out, "w") as f:
+            json.dump({"recipe": "stress128g, 4096x4096x2048 (2^35 voxels)",
+                       "oracle_mean": ref.mean, "oracle_std": ref.std,
+                       "oracle_seconds": t_oracle, "threads": host_threads(),
+                       "rel_err_mean_std": {k: list(v) for k, v in modes.items()}}, f, indent=1)
+    golden = os.path.join(os.path.dirname(__file__), "golden", "stress128g_oracle.json")
+    if os.path.exists(golden):
+        import dataclasses
+        import json
+        from tests.golden.make_stress128g_oracle import generator_hash
+        g = json.load(open(golden))
+        if g["generator_sha256_16"] == generator_hash() and g["seed"] == synth.BASE_SEED + 4:
+            # the stored oracle values are those of this cube, bit for bit
+            assert g["stats"] == dataclasses.asdict(ref), (g["stats"], ref)
 
     # sub-boxes against the oracle, including the far end of the cube
     for sl in (np.s_[0:2], np.s_[nz // 2:nz // 2 + 2, 100:3000, 7:4001], np.s_[nz - 2:nz]):
@@ -214,7 +258,7 @@ def test_serving_full_size(cs):
     minmax-histogram queries.  Every served result equals the single-box
     calls bit for bit (same tiling-independent counts and extrema, same
     statistics bytes when the single-box pass is run as a one-query batch);
-    a few small sub-boxes are checked against the oracle."""
+    the 50 smallest served queries are checked against the oracle."""
     import threading
 
     import synth
@@ -281,14 +325,23 @@ def test_serving_full_size(cs):
             elif kind == cs.CUBE_Q_MINMAX:
                 _, cm = cs.stats_hist_minmax(v, nb)
                 assert np.array_equal(cnt[i, :nb + 3].cpu().numpy().view(np.uint64), cm)
-        # small sub-boxes against the oracle
-        small = sorted(range(n), key=lambda i: specs[i].voxels)[:3]
+        # the 50 smallest served queries against the oracle (statistics of
+        # every one, streamed to host threads; counts of those up to 2^27
+        # voxels)
+        small = sorted(range(n), key=lambda i: specs[i].voxels)[:50]
         for i in small:
             v, kind, nb, lo, hi = views[i]
-            host = v.cpu().numpy()
-            ref = oracle.stats(host)
-            assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref,
-                               f"served query {i}")
+            ref = oracle_stats_of_device(oracle, v)
+            if kind != cs.CUBE_Q_HIST:
+                assert_stats_match(cs.Stats.from_bytes(out[i].cpu().numpy().tobytes()), ref,
+                                   f"served query {i}")
+            if kind != cs.CUBE_Q_STATS and v.numel() <= (1 << 27):
+                host = v.cpu().numpy()
+                want = oracle.hist(host, lo, hi, nb) if kind != cs.CUBE_Q_MINMAX else \
+                    oracle.hist(host, ref.min, ref.max, nb) if ref.n_valid else None
+                if want is not None:
+                    assert_counts_match(cnt[i, :nb + 3].cpu().numpy().view(np.uint64), want,
+                                        f"served query {i} counts")
     finally:
         del cubes
         torch.cuda.empty_cache()

@@ -41,8 +41,8 @@ def test_tiny_workload_64_levels(cs):
 
 def test_many_leading_buckets(cs):
     """Values spread over 2^-60 .. 2^60 of both signs: the 64 levels' ranks
-    fall in dozens of distinct top-12-bit key buckets, so the middle pass
-    runs several times (eight buckets per read)."""
+    fall in dozens of distinct top-12-bit key buckets, so the call takes the
+    12 + 8 + 6 + 6-bit passes (four reads of the box)."""
     rng = np.random.default_rng(17)
     n = 300_000
     a = (np.exp2(rng.uniform(-60, 60, n)) * rng.choice([-1, 1], n)).astype(np.float32)
@@ -52,6 +52,7 @@ def test_many_leading_buckets(cs):
     got, nv = cs.quantiles(t, levels)
     assert nv == int((~np.isnan(a)).sum())
     assert same(got, oracle.quantiles(a, levels))
+    assert cs.cube_last_quantile_reads() == 4
 
 
 @pytest.mark.parametrize("groups", [1, 8, 9, 64])
@@ -74,6 +75,7 @@ def test_bucket_count_boundary(cs, groups):
     got, nv = cs.quantiles(t, levels)
     assert nv == n
     assert same(got, oracle.quantiles(a, levels))
+    assert cs.cube_last_quantile_reads() == (3 if groups <= 8 else 4)
 
 
 def test_many_ranks_in_few_buckets(cs):
@@ -90,6 +92,7 @@ def test_many_ranks_in_few_buckets(cs):
     got, nv = cs.quantiles(t, levels)
     assert nv == a.size
     assert same(got, oracle.quantiles(a, levels))
+    assert cs.cube_last_quantile_reads() == 4
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 2), (3, 1, 1), (7, 5, 301), (64, 64, 128),

@@ -37,6 +37,12 @@ MUTANTS = {
                                  "if (0) {\n                    /* kept apart"),
     "inf_both_signs_not_nan": ("if (s->n_pinf && s->n_ninf) return NAN;", ""),
     "inf_std_finite": ("out->m2 = out->std = NAN;\n        return;", "out->m2 = out->std = 0.0;"),
+    "slab_min_from_empty": ("if (a->n_valid == 0) {\n            a->min = b->min;\n            a->max = b->max;\n        } else {",
+                            "{"),
+    "slab_max_order": ("if (before(a->max, b->max)) a->max = b->max;",
+                       "if (before(b->max, a->max)) a->max = b->max;"),
+    "slab_sum_compensation_dropped": ("a->sum_c += b->sum_c;", ""),
+    "slab_sq_not_added": ("neumaier_add(&a->sq, &a->sq_c, b->sq);", ""),
     "clamp_off_by_one": ("if (b > nbins - 1) b = nbins - 1;", "if (b > nbins) b = nbins;"),
     "below_above_swapped": ("counts[nbins]++;\n                } else if (v > hi) {\n                    counts[nbins + 1]++;",
                             "counts[nbins + 1]++;\n                } else if (v > hi) {\n                    counts[nbins]++;"),
