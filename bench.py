@@ -146,10 +146,12 @@ def cpu_baseline(cube, nbins: int, lo: float, hi: float, target_s: float):
             "host_cores": os.cpu_count()}
 
 
-def bench_batch64(cs, synth, torch, dev, steps: int):
+def bench_batch64(cs, synth, torch, dev, steps: int, tune: bool = False):
     """64 uneven items, each statistics then a 512-bin histogram over its own
     [min, max]: one persistent launch replayed from a HIP graph, against the
-    plain per-item calls (two launches each) on one stream."""
+    plain per-item calls (two launches each) on one stream.  The timed batch
+    runs the automatic rule (the tuning table's, or a fresh autotune with
+    `tune`); fixed tile sizes are swept beside it for context."""
     import numpy as np
     recs = synth.batch_item_recipes()
     items = [synth.cube_tensor(r, synth.BASE_SEED + 2 + i, device=dev) for i, r in enumerate(recs)]
@@ -163,17 +165,18 @@ def bench_batch64(cs, synth, torch, dev, steps: int):
     boxes = [cs.box_of(t) for t in items]
     qs = [cs.make_query(p, d, cs.CUBE_Q_MINMAX, nb, 0.0, 0.0, out[i].data_ptr(), cnt[i].data_ptr())
           for i, (p, d) in enumerate(boxes)]
-    # tile size: the fastest of a few (graph-replayed)
+    tuned = cs.cube_autotune_batch(qs, reps=5) if tune else None
+    # fixed tile sizes beside the automatic rule (graph-replayed), for context
     tiles = {}
-    for tv in (0, 1 << 16, 1 << 17, 1 << 18, 1 << 20):     # 0: each item's automatic size
+    for tv in (1 << 16, 1 << 17, 1 << 18, 1 << 20):
         b = cs.Batch(tile_voxels=tv)
         b.enqueue(qs, sp)
         b.check()
         _, ms = time_launches(lambda: b.graph_launch(sp), stream, max(5, steps // 3), 2)
         tiles[tv] = ms
         b.close()
-    best_tile = min(tiles, key=tiles.get)
-    b = cs.Batch(tile_voxels=best_tile)
+    # the timed batch: automatic tile and threads (the tuned rule, if any)
+    b = cs.Batch(tile_voxels=0, threads=0)
     b.enqueue(qs, sp)
     b.check()
     _, ev_b = time_launches(lambda: b.graph_launch(sp), stream, steps, 3)
@@ -197,8 +200,9 @@ def bench_batch64(cs, synth, torch, dev, steps: int):
         worst = max(worst, abs(a.std - c.std) / c.std)
     b.close()
     del items
-    return {"items": n, "voxels": nvox, "nbins": nb, "tile_voxels": best_tile,
-            "tile_sweep_ms": {str(k): round(v, 4) for k, v in tiles.items()},
+    return {"items": n, "voxels": nvox, "nbins": nb, "rule": "automatic (tuned rule if loaded)",
+            "autotune": tuned,
+            "fixed_tile_sweep_ms": {str(k): round(v, 4) for k, v in tiles.items()},
             "batched_graph_ms": ev_b, "plain_ms": ev_p,
             "batched_voxels_per_s": nvox / (ev_b * 1e-3), "plain_voxels_per_s": nvox / (ev_p * 1e-3),
             "speedup": ev_p / ev_b, "counts_and_extrema_equal": counts_equal,
@@ -520,6 +524,9 @@ def main() -> int:
     ap.add_argument("--no-stress", action="store_true", help="skip the 128 GiB stress cube")
     ap.add_argument("--no-select", action="store_true", help="skip selection and median")
     ap.add_argument("--no-host", action="store_true", help="skip the out-of-core host queries")
+    ap.add_argument("--only-stress", action="store_true",
+                    help="time the 128 GiB stress cube's fused pass only and print its record "
+                         "(for profiler runs; not the benchmark line)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the replayed query stream (at least 10^4 queries)")
     ap.add_argument("--serve-sweep", default="",
@@ -541,6 +548,13 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     if args.launch:
         cs.cube_set_launch(*[int(v) for v in args.launch.split(",")])
+    if args.only_stress:
+        table = os.path.join(ROOT, TUNE_TABLE)
+        if not (args.no_tune or args.launch) and os.path.exists(table):
+            cs.cube_tune_load(table)
+        rec = bench_stress(cs, synth, torch, dev, args.steps)
+        print(json.dumps({"stress128g": rec}), flush=True)
+        return 0
     name = "brick16g"
     r = synth.WORKLOADS[name]
     nbins = synth.HIST_BINS[name]
@@ -634,7 +648,8 @@ def main() -> int:
         extra["tuning"] = tuned
     if not args.only_fused and not args.no_batch:
         log("batch64 ...")
-        extra["batch64"] = bench_batch64(cs, synth, torch, dev, max(10, args.steps // 2))
+        extra["batch64"] = bench_batch64(cs, synth, torch, dev, max(10, args.steps // 2),
+                                         tune=mode == "run")
         log(f"batch64: graph {extra['batch64']['batched_graph_ms']:.3f} ms vs plain "
             f"{extra['batch64']['plain_ms']:.3f} ms")
     if not args.only_fused and not args.no_select:

@@ -202,6 +202,25 @@ CUBE_API int cube_set_accum_mode(int32_t mode);
 CUBE_API int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll);
 
 /*
+ * Form of the LDS histogram for later single-box histogram passes from the
+ * CALLING THREAD (each thread starts with CUBE_HIST_AUTO):
+ *   CUBE_HIST_AUTO  the autotuner's choice for the call's class, else plain;
+ *   CUBE_HIST_PLAIN every in-range voxel is one LDS atomic;
+ *   CUBE_HIST_HOT   each block keeps one hot bin (the bin of the first
+ *                   in-range voxel it reads) out of LDS and counts it as its
+ *                   in-range total minus the other bins: far fewer LDS
+ *                   atomics on a skewed histogram, a few more scalar
+ *                   instructions per voxel otherwise.
+ * Counts are identical in every form.  Histograms of more than 32768 bins
+ * use global atomics whatever the form.  Returns the previous form of the
+ * thread, or CUBE_EINVAL for an unknown one.
+ */
+#define CUBE_HIST_AUTO 0
+#define CUBE_HIST_PLAIN 1
+#define CUBE_HIST_HOT 2
+CUBE_API int cube_set_hist_mode(int32_t mode);
+
+/*
  * Exact selection and median (Section 3 names the median as a global,
  * multi-pass task).  cube_select stores in *value the valid voxel of rank
  * `rank` (0-based) in the order by value with -0 before +0; CUBE_EINVAL if
@@ -306,9 +325,19 @@ CUBE_API int cube_tune_save(const char *path);
 CUBE_API int cube_tune_load(const char *path);
 CUBE_API void cube_tune_clear(void);
 
-/* Release every workspace on every device (synchronises each stream that
- * owns one).  The library stays usable; workspaces are made again on demand. */
+/* Release every workspace on every device (waiting for the last work queued
+ * with each).  The library stays usable; workspaces are made again on demand. */
 CUBE_API void cube_shutdown(void);
+
+/* The single-box calls keep one workspace (about 2 MiB of device and pinned
+ * memory) per (device, stream) they were given, until cube_shutdown.  Call
+ * this before destroying a stream that was passed to them: it waits for the
+ * stream's last call and frees its workspaces (a later call on the same
+ * stream makes a new one).  Not concurrently with calls on that stream.  A
+ * stream handle that is destroyed and then reused by a new stream must be
+ * released in between, or the new stream inherits the old one's workspace.
+ * NULL is the default stream.  Never fails. */
+CUBE_API void cube_release_stream(void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched queries in one persistent launch (the paper's batched analysis
@@ -385,6 +414,25 @@ CUBE_API int cube_batch_check(cube_batch_t *b);
 /* Synchronous convenience: create, enqueue on the default stream, check,
  * destroy. */
 CUBE_API int cube_batch_run(const cube_query_t *q, int32_t n);
+
+/*
+ * Autotuner of the batched launch.  Times candidate automatic rules -- threads
+ * per block (256, 512, 1024), each query's tile size as a function of its
+ * own voxel count (a floor of 2^16..2^18 voxels, doubled up to a cap of
+ * 2^19..2^21 while the query needs more than 2^8..2^10 tiles) and the LDS
+ * budget of the histogram copies (64 or 128 KiB) -- as graph-replayed
+ * launches of a batch of the caller's n queries (`reps` timed replays each;
+ * the queries' device outputs are overwritten), and keeps the fastest as the
+ * rule for every later batch whose tile size and threads are automatic
+ * (cube_batch_set_tile(b, 0, 0); the server's default).  One rule serves all
+ * batches, so a query's tiling depends on the query alone.  The rule is
+ * saved and loaded with the tuning table.  If `report` is not NULL, a JSON
+ * summary is written there.  Errors: those of cube_batch_enqueue; CUBE_EINVAL
+ * for n < 1 or reps outside [1, 100].
+ */
+CUBE_API int cube_autotune_batch(const cube_query_t *q, int32_t n, int32_t reps, char *report,
+                                 size_t report_cap);
+
 
 /*
  * Out-of-core query over a cube in HOST memory.  The paper's cubes exceed

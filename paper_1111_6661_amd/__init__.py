@@ -28,6 +28,7 @@ CUBE_OK, CUBE_EINVAL, CUBE_ENOMEM, CUBE_EDEVICE, CUBE_EBUSY = 0, -1, -2, -3, -4
 CUBE_MAX_BINS = 65536
 CUBE_NO_VALID, CUBE_HIST_BAD_RANGE = 1, 2
 CUBE_ACCUM_FP64MERGE, CUBE_ACCUM_KAHAN32, CUBE_ACCUM_NAIVE32 = 0, 1, 2
+CUBE_HIST_AUTO, CUBE_HIST_PLAIN, CUBE_HIST_HOT = 0, 1, 2
 
 
 class CubeError(RuntimeError):
@@ -103,7 +104,10 @@ def load() -> C.CDLL:
     lib.cube_stats_hist_noalloc.argtypes = [P, I64P, f32, f32, i32, P, P, P]
     lib.cube_set_accum_mode.argtypes = [i32]
     lib.cube_set_launch.argtypes = [i32, i32, i32, i32]
+    lib.cube_set_hist_mode.argtypes = [i32]
     lib.cube_shutdown.restype = None
+    lib.cube_release_stream.argtypes = [P]
+    lib.cube_release_stream.restype = None
     lib.cube_batch_create.argtypes = [C.POINTER(C.c_void_p)]
     lib.cube_batch_destroy.argtypes = [P]
     lib.cube_batch_destroy.restype = None
@@ -136,6 +140,8 @@ def load() -> C.CDLL:
     lib.cube_last_quantile_reads.restype = C.c_int
     lib.cube_autotune.argtypes = [P, I64P, i32, f32, f32, i32, i32, C.c_char_p, C.c_size_t]
     lib.cube_autotune.restype = C.c_int
+    lib.cube_autotune_batch.argtypes = [C.POINTER(cube_query_t), i32, i32, C.c_char_p, C.c_size_t]
+    lib.cube_autotune_batch.restype = C.c_int
     lib.cube_tune_save.argtypes = [C.c_char_p]
     lib.cube_tune_save.restype = C.c_int
     lib.cube_tune_load.argtypes = [C.c_char_p]
@@ -154,7 +160,7 @@ def load() -> C.CDLL:
     for name in ("cube_stats", "cube_hist", "cube_stats_hist", "cube_stats_hist_minmax",
                  "cube_stats_async", "cube_hist_async", "cube_stats_hist_async",
                  "cube_stats_hist_minmax_async", "cube_stats_hist_noalloc",
-                 "cube_set_accum_mode", "cube_set_launch"):
+                 "cube_set_accum_mode", "cube_set_launch", "cube_set_hist_mode"):
         getattr(lib, name).restype = C.c_int
     if lib.cube_abi_version() != 1:
         raise RuntimeError("libcubestats ABI version mismatch")
@@ -247,6 +253,11 @@ def cube_set_accum_mode(mode: int) -> int:
     return _check(load().cube_set_accum_mode(mode))
 
 
+def cube_set_hist_mode(mode: int) -> int:
+    """Histogram form of this thread's later single-box passes; returns the previous one."""
+    return _check(load().cube_set_hist_mode(mode))
+
+
 def cube_set_launch(threads: int = 0, blocks: int = 0, hist_copies: int = 0,
                     unroll: int = 0) -> None:
     _check(load().cube_set_launch(threads, blocks, hist_copies, unroll))
@@ -309,6 +320,16 @@ def cube_autotune(ptr: int, dims, kind: int, lo: float = 0.0, hi: float = 0.0, n
     return json.loads(buf.value.decode())
 
 
+def cube_autotune_batch(queries, reps: int = 5) -> dict:
+    """Tune the batched launch's automatic rule on these queries (their
+    device outputs are overwritten); returns the autotuner's JSON report."""
+    import json
+    arr = (cube_query_t * len(queries))(*queries)
+    buf = C.create_string_buffer(1024)
+    _check(load().cube_autotune_batch(arr, len(queries), reps, buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
 def cube_tune_save(path: str) -> None:
     _check(load().cube_tune_save(path.encode()))
 
@@ -323,6 +344,11 @@ def cube_tune_clear() -> None:
 
 def cube_shutdown() -> None:
     load().cube_shutdown()
+
+
+def cube_release_stream(stream: int) -> None:
+    """Free the workspace the single-box calls keep for this stream."""
+    load().cube_release_stream(C.c_void_p(stream))
 
 
 # ------------------------------------------------------------ tensor helpers

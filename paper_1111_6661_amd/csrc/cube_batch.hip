@@ -27,6 +27,7 @@
 // Results of a query do not depend on the other queries of the batch (its
 // tiling and merge order are its own), so a query gives the same bits alone
 // and in any mix.
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -108,11 +109,19 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
     __syncthreads();
     const unsigned int tag = s_tag;
 
+    // Tiles are claimed one ahead: thread 0 takes the next tile's index as
+    // the current one starts, so the claim's round trip overlaps the scan.
+    // A claimed first-phase tile is always held by a block working on an
+    // earlier first-phase tile (every first-phase tile precedes every
+    // second-phase tile in the list), which never waits, so every first-phase
+    // tile is still processed and second-phase waits end.
+    if (tid == 0) s_tile = (int)atomicAdd(&a.ctl[0], 1u);
+    __syncthreads();
     while (true) {
-        if (tid == 0) s_tile = (int)atomicAdd(&a.ctl[0], 1u);
-        __syncthreads();
         const int t = s_tile;
         if (t >= a.n_tiles) break;
+        unsigned int next = 0u;
+        if (tid == 0) next = atomicAdd(&a.ctl[0], 1u);
         const BatchTile tile = a.tiles[t];
         const BatchItem &it = a.items[tile.item];
         BatchState *st = &a.state[tile.item];
@@ -171,16 +180,19 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         const long long rec0 = tile.phase == 1 ? it.rec1 : it.rec2;
         WaveRec *recs = a.recs + rec0;
         if (stats)
-            write_wave_record<true, CUBE_ACCUM_FP64MERGE>(L, W, &recs[(long long)tile.local * nw + wid]);
+            write_wave_record<true, CUBE_ACCUM_FP64MERGE, true>(
+                L, W, &recs[(long long)tile.local * nw + wid]);
         else
-            write_wave_record<false, CUBE_ACCUM_FP64MERGE>(L, W, &recs[(long long)tile.local * nw + wid]);
+            write_wave_record<false, CUBE_ACCUM_FP64MERGE, true>(
+                L, W, &recs[(long long)tile.local * nw + wid]);
         if (hist) hist_flush(lds, it.nbins, a.copies_log2, acc);
 
-        // Completion of the query's phase: the last tile merges.  One
-        // release fence per block (see last_to_arrive).
+        // Completion of the query's phase: the last tile merges.  The records
+        // are written through the L2 and the counts are atomics, so no L2
+        // write-back is needed (see last_to_arrive_wt).
         const int ntiles = tile.phase == 1 ? it.ntiles1 : it.ntiles2;
-        if (last_to_arrive(tile.phase == 1 ? &st->done1 : &st->done2, (unsigned int)ntiles,
-                           &s_flag)) {
+        if (last_to_arrive_wt(tile.phase == 1 ? &st->done1 : &st->done2, (unsigned int)ntiles,
+                              &s_flag)) {
             const int n_recs = ntiles * nw;
             unsigned long long nv, below, above;
             if (stats) {
@@ -227,6 +239,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                 }
             }
         }
+        if (tid == 0) s_tile = (int)next;
         __syncthreads();
     }
 
@@ -241,6 +254,14 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
 }
 
 // ------------------------------------------------------------------ host side
+long long rule_tile_voxels(const BatchRule &r, unsigned long long n)
+{
+    long long tv = (long long)1 << r.floor_log2;
+    while (tv < ((long long)1 << r.cap_log2) && (unsigned long long)tv << r.tiles_log2 < n)
+        tv <<= 1;
+    return tv;
+}
+
 static hipError_t batch_occupancy(int threads, size_t lds, int *bpc)
 {
     const void *k = reinterpret_cast<const void *>(&k_batch);
@@ -282,9 +303,12 @@ struct cube_batch {
     int order = 0;                  // 0 largest queries first, 1 smallest first
     bool have_work = false;
     BatchArgs args;
-    int threads = 512, blocks = 0;
+    int threads_req = 0;             // 0: the rule's
+    int threads = 512, blocks = 0;   // of the current work list
     size_t lds = 0;
-    long long tile_voxels = 1 << 20;
+    long long tile_voxels = 1 << 20; // 0: the rule's, per query
+    bool have_rule = false;          // the autotuner's candidate, else the table's
+    BatchRule rule = DEFAULT_BATCH_RULE;
     hipGraph_t graph = nullptr;       // the launch, captured once per work list;
     hipGraphExec_t graph_exec = nullptr;  // replayed on any stream
 };
@@ -469,7 +493,7 @@ int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads)
         return fail(CUBE_EINVAL, "threads must be 0, 256, 512 or 1024");
     std::lock_guard<std::mutex> lk(b->mu);
     b->tile_voxels = tile_voxels;
-    b->threads = threads ? threads : 512;
+    b->threads_req = threads;
     return CUBE_OK;
 }
 
@@ -485,6 +509,14 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     std::vector<long long> order((size_t)n);
     size_t n_tiles = 0, n_recs = 0, n_acc = 0;
     int max_bins = 1;
+    // The automatic rule: the autotuner's candidate, else the tuned one,
+    // else the defaults.
+    BatchRule rule = DEFAULT_BATCH_RULE;
+    if (b->have_rule)
+        rule = b->rule;
+    else
+        tuned_batch_rule(&rule);
+    b->threads = b->threads_req ? b->threads_req : rule.threads;
     const int nw = b->threads / 64;
     for (int i = 0; i < n; ++i) {
         const cube_query_t &qq = q[i];
@@ -517,15 +549,13 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
         it.counts = (unsigned long long *)qq.counts;
         collapse(box, &it.g);
         // The query's tile size: the batch's, or (0) one from the query's own
-        // size, at most 512 tiles with 2^18 to 2^20 voxels each.  Below 2^18
-        // the per-tile completion (a release fence and a ticket) costs more
-        // than the parallelism it buys.  Either way a query's tiling depends
-        // only on itself, so its results are the same alone and in any mix.
+        // size by the rule (by default at most 512 tiles of 2^18 to 2^20
+        // voxels: below 2^18 the per-tile completion, a release fence and a
+        // ticket, costs more than the parallelism it buys).  Either way a
+        // query's tiling depends only on itself, so its results are the same
+        // alone and in any mix.
         long long tv = b->tile_voxels;
-        if (tv == 0) {
-            tv = (long long)1 << 18;
-            while (tv < ((long long)1 << 20) && tv * 512 < (long long)box.n) tv <<= 1;
-        }
+        if (tv == 0) tv = rule_tile_voxels(rule, box.n);
         // Segments of at most one tile; whole rows per tile when rows are short.
         Geom &g = it.g;
         long long seg = g.row_len < tv ? g.row_len : tv;
@@ -599,7 +629,8 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     // Launch shape: one histogram copy layout for the batch, a grid of
     // resident blocks.
     int clog = 0;
-    while (clog < 5 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= 64 * 1024) ++clog;
+    const size_t lds_budget = (size_t)rule.lds_kib * 1024;
+    while (clog < 5 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= lds_budget) ++clog;
     b->lds = ((size_t)(max_bins + 2) << clog) * 4;
     int bpc = 1;
     if ((e = batch_occupancy(b->threads, b->lds, &bpc)) != hipSuccess)
@@ -722,6 +753,84 @@ int cube_batch_check(cube_batch_t *b)
                                   "range; its histogram is incomplete");
     }
     return CUBE_OK;
+}
+
+int cube_autotune_batch(const cube_query_t *q, int32_t n, int32_t reps, char *report,
+                        size_t report_cap)
+{
+    CUBE_GUARD_BEGIN
+    if (n < 1 || !q) return fail(CUBE_EINVAL, "autotune needs at least one query");
+    if (reps < 1 || reps > 100) return fail(CUBE_EINVAL, "reps outside [1, 100]");
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "tune stream");
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        hipStreamDestroy(s);
+        return hip_fail(e, "tune events");
+    }
+    cube_batch_t *b = nullptr;
+    int rc = cube_batch_create(&b);
+    std::vector<BatchRule> cands;
+    for (int th : {256, 512, 1024})
+        for (int fl : {16, 17, 18})
+            for (int cp : {19, 20, 21})
+                for (int tl : {8, 9, 10})
+                    for (int kib : {64, 128}) cands.push_back(BatchRule{th, fl, cp, tl, kib, 0.f});
+    BatchRule best = DEFAULT_BATCH_RULE, worst = DEFAULT_BATCH_RULE;
+    best.ms = 1e30f;
+    worst.ms = -1.f;
+    for (size_t i = 0; !rc && i < cands.size(); ++i) {
+        BatchRule &c = cands[i];
+        {
+            std::lock_guard<std::mutex> lk(b->mu);
+            b->have_rule = true;
+            b->rule = c;
+            b->tile_voxels = 0;
+            b->threads_req = 0;
+        }
+        // enqueue launches once (warm-up); the first graph launch captures
+        if ((rc = cube_batch_enqueue(b, q, n, s))) break;
+        if ((rc = cube_batch_graph_launch(b, s))) break;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) { rc = hip_fail(e, "tune event"); break; }
+        for (int k = 0; k < reps && !rc; ++k) rc = cube_batch_graph_launch(b, s);
+        if (rc) break;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+            rc = hip_fail(e, "tune synchronize");
+            break;
+        }
+        if ((rc = cube_batch_check(b))) break;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        c.ms = ms / reps;
+        if (c.ms < best.ms) best = c;
+        if (c.ms > worst.ms) worst = c;
+    }
+    if (b) cube_batch_destroy(b);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(s);
+    if (rc) return rc;
+    set_tuned_batch_rule(best);
+    if (report && report_cap) {
+        char buf[512];
+        auto fmt = [](const BatchRule &r, char *out, size_t cap) {
+            snprintf(out, cap,
+                     "{\"threads\": %d, \"floor_log2\": %d, \"cap_log2\": %d, "
+                     "\"tiles_log2\": %d, \"lds_kib\": %d, \"ms\": %.5f}",
+                     r.threads, r.floor_log2, r.cap_log2, r.tiles_log2, r.lds_kib, r.ms);
+        };
+        char sb[200], sw[200];
+        fmt(best, sb, sizeof sb);
+        fmt(worst, sw, sizeof sw);
+        snprintf(buf, sizeof buf, "{\"best\": %s, \"worst\": %s, \"candidates\": %zu}", sb, sw,
+                 cands.size());
+        snprintf(report, report_cap, "%s", buf);
+    }
+    return CUBE_OK;
+    CUBE_GUARD_END
 }
 
 int cube_batch_run(const cube_query_t *q, int32_t n)

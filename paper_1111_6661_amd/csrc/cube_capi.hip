@@ -68,6 +68,10 @@ thread_local int g_accum = CUBE_ACCUM_FP64MERGE;
 int accum_mode() { return g_accum; }
 
 thread_local int g_threads = 0, g_blocks = 0, g_copies = 0, g_unroll = 0;
+thread_local int g_hot = -1;
+
+void set_hot_override(int hot) { g_hot = hot; }
+int hot_override() { return g_hot; }
 
 void get_launch(int *threads, int *blocks, int *copies, int *unroll)
 {
@@ -96,6 +100,7 @@ struct Workspace {
     HistRange *d_range = nullptr;
     cube_stats_t *h_out = nullptr;        // pinned
     unsigned long long *h_counts = nullptr;
+    hipEvent_t used = nullptr;            // recorded after the last work queued with it
     std::mutex mu;                        // held by synchronous calls
 };
 
@@ -103,12 +108,17 @@ std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 std::map<int, int> g_cus;
 
+// Waits for the last work queued with the workspace through its event, not
+// through its stream: the caller may have destroyed that stream already.
 void free_ws(Workspace *w)
 {
     int prev = 0;
     hipGetDevice(&prev);
     hipSetDevice(w->device);
-    hipStreamSynchronize(w->stream);
+    if (w->used) {
+        hipEventSynchronize(w->used);
+        hipEventDestroy(w->used);
+    }
     hipFree(w->recs);
     hipFree(w->ticket);
     hipFree(w->hist_acc);
@@ -137,7 +147,8 @@ int get_ws(hipStream_t s, Workspace **out)
     w->device = dev;
     w->stream = s;
     const size_t nacc = (size_t)CUBE_MAX_BINS + 3;
-    bool ok = hipMalloc(&w->recs, REC_CAP * sizeof(WaveRec)) == hipSuccess &&
+    bool ok = hipEventCreateWithFlags(&w->used, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc(&w->recs, REC_CAP * sizeof(WaveRec)) == hipSuccess &&
               hipMalloc(&w->ticket, 256) == hipSuccess &&
               hipMalloc(&w->hist_acc, nacc * 8) == hipSuccess &&
               hipMalloc(&w->d_out, sizeof(cube_stats_t)) == hipSuccess &&
@@ -159,6 +170,32 @@ int get_ws(hipStream_t s, Workspace **out)
     g_ws[key] = w;
     *out = w;
     return CUBE_OK;
+}
+
+// Record that work using `w` was queued on `s` (after a successful enqueue).
+int mark_ws(Workspace *w, hipStream_t s)
+{
+    const hipError_t e = hipEventRecord(w->used, s);
+    return e == hipSuccess ? CUBE_OK : hip_fail(e, "workspace event");
+}
+
+// Free the workspaces of stream `s` (one per device it was used on; a live
+// stream handle names one stream process-wide).
+void release_ws(hipStream_t s)
+{
+    std::vector<Workspace *> gone;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto it = g_ws.begin(); it != g_ws.end();) {
+            if (it->first.second == s) {
+                gone.push_back(it->second);
+                it = g_ws.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    for (Workspace *w : gone) free_ws(w);
 }
 
 int cu_count()
@@ -334,13 +371,16 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
     // With no explicit shape, use the autotuner's choice for this class.
     TunedShape ts;
     const int kind = stats ? (hist_kind_req ? CUBE_Q_FUSED : CUBE_Q_STATS) : CUBE_Q_HIST;
+    int hot = 0;
     if (threads == 0 && unroll == 0 && copies_req == 0 && blocks == 0 &&
         tuned_shape(kind, hist_kind_req ? nbins : 1, b.n, &ts)) {
         threads = ts.threads;
         unroll = ts.unroll;
         copies_req = ts.copies;
         blocks = (long long)cu_count() * ts.blocks_per_cu;
+        hot = ts.hot;
     }
+    if (g_hot >= 0) hot = g_hot;
     // Histogram passes over boxes under 2^25 voxels default to 256 threads:
     // their launches are short enough that per-block costs dominate (below).
     const bool small = b.n < ((uint64_t)1 << 25);
@@ -365,6 +405,7 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
             }
             while (clog > 0 && ((size_t)(nbins + 2) << clog) * 4 > 160 * 1024) --clog;
             p->copies_log2 = clog;
+            if (hot) p->hist = HIST_HOT;
         }
     }
     p->lds = pass_lds_bytes(stats, p->hist, nbins, p->copies_log2, threads);
@@ -528,7 +569,8 @@ int run_pass(const Box &b, bool stats, bool hist, int nbins, const HistRange &ra
     a.out = stats ? dev_out : nullptr;
     a.counts = hist ? dev_counts : nullptr;
     a.accumulate = accumulate ? 1 : 0;
-    return launch(a, p, stats, s);
+    if ((rc = launch(a, p, stats, s))) return rc;
+    return mark_ws(w, s);
 }
 
 int write_empty(cube_stats_t *dev_out, unsigned long long *dev_counts, int nbins, hipStream_t s)
@@ -574,6 +616,7 @@ int run_sync(Op op, const float *ptr, const int64_t *dims, float lo, float hi, i
                             hipMemcpyDeviceToHost, nullptr)) != hipSuccess)
         return hip_fail(e, "counts copy");
     if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e, "synchronize");
+    if ((rc = mark_ws(w, nullptr))) return rc;
     if (op != OP_HIST) *out = *w->h_out;
     if (op != OP_STATS) memcpy(counts, w->h_counts, ((size_t)nbins + 3) * 8);
     if (op == OP_MINMAX && (w->h_out->flags & CUBE_HIST_BAD_RANGE))
@@ -591,8 +634,10 @@ int run_async_entry(Op op, const float *ptr, const int64_t *dims, float lo, floa
     Workspace *w = nullptr;
     rc = get_ws((hipStream_t)stream, &w);
     if (rc) return rc;
-    return run_async(op, ptr, dims, lo, hi, nbins, dev_out, (unsigned long long *)dev_counts,
-                     (hipStream_t)stream, w);
+    rc = run_async(op, ptr, dims, lo, hi, nbins, dev_out, (unsigned long long *)dev_counts,
+                   (hipStream_t)stream, w);
+    if (rc) return rc;
+    return mark_ws(w, (hipStream_t)stream);
 }
 
 }  // namespace cube
@@ -688,6 +733,15 @@ int cube_set_accum_mode(int32_t mode)
     return prev;
 }
 
+int cube_set_hist_mode(int32_t mode)
+{
+    if (mode != CUBE_HIST_AUTO && mode != CUBE_HIST_PLAIN && mode != CUBE_HIST_HOT)
+        return fail(CUBE_EINVAL, "unknown histogram form %d", mode);
+    const int prev = g_hot < 0 ? CUBE_HIST_AUTO : (g_hot ? CUBE_HIST_HOT : CUBE_HIST_PLAIN);
+    g_hot = mode == CUBE_HIST_AUTO ? -1 : (mode == CUBE_HIST_HOT ? 1 : 0);
+    return prev;
+}
+
 int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll)
 {
     if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
@@ -702,6 +756,13 @@ int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_
     g_copies = hist_copies;
     g_unroll = unroll;
     return CUBE_OK;
+}
+
+void cube_release_stream(void *stream)
+{
+    CUBE_GUARD_BEGIN
+    release_ws((hipStream_t)stream);
+    CUBE_GUARD_VOID_END
 }
 
 void cube_shutdown(void)

@@ -91,12 +91,48 @@ struct Wave {  // wavefront-uniform
 // the min(nbins-1, .) of the bin rule).  The byte address of bin b for a
 // lane is (b << shift) + base with base = (C + lane % C) * 4, so the dummy
 // slot is b = -1, an inline constant.
+//
+// With a hot bin (HIST_HOT), lanes whose bin is the block's hot bin add
+// nothing to LDS; out-of-range and blank lanes are masked off instead of
+// going to the dummy slot.
 struct Hist {
     float lo, hi, scale;
     int nbins, shift, base;
+    int hot;  // HIST_HOT: the block's hot bin (0..nbins), or -2 for none
+    unsigned int base_abs;  // HIST_HOT: base plus the LDS byte address of `lds`
     unsigned int *lds;
     unsigned long long *global;
 };
+
+// LDS word at byte address `addr` += 1 in the lanes of `m` only: the exec
+// mask is narrowed around one ds_add_u32 and restored in the same asm block,
+// so the step stays one basic block (a compiler branch per voxel splits the
+// loop into small blocks and spills its lane masks).  The compiler does not
+// count this LDS operation: whoever reads the histogram waits for it with
+// lds_wait() first.
+__device__ __forceinline__ void lds_add1_masked(unsigned int addr, unsigned long long m)
+{
+    unsigned long long saved;
+    asm volatile(
+        "s_and_saveexec_b64 %0, %1\n\t"
+        "ds_add_u32 %2, %3\n\t"
+        "s_or_b64 exec, exec, %0"
+        : "=&s"(saved)
+        : "s"(m), "v"(addr), "v"(1u)
+        : "memory", "scc");
+}
+
+__device__ __forceinline__ void lds_wait()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// The byte address of an LDS pointer (the LDS aperture keeps the offset in
+// the low 32 bits of a generic address).
+__device__ __forceinline__ unsigned int lds_offset(const unsigned int *p)
+{
+    return (unsigned int)(size_t)(__attribute__((address_space(3))) const unsigned int *)p;
+}
 
 // m[lane] ? v : 0, and m[lane] ? v : -1 -- one v_cndmask_b32 reading a
 // ballot mask directly, so a mask a ballot already produced is reused.
@@ -141,9 +177,10 @@ __device__ __forceinline__ void process(const float (&x)[NV], Lane &L, Wave &W,
     for (int j = 0; j < NV; ++j) {
         const float v = x[j];
         unsigned long long mvalid, inr = 0;
+        const bool ge = v >= H.lo, le = v <= H.hi;
         if (HIST != HIST_NONE) {
-            const unsigned long long mge = __builtin_amdgcn_ballot_w64(v >= H.lo);
-            const unsigned long long mle = __builtin_amdgcn_ballot_w64(v <= H.hi);
+            const unsigned long long mge = __builtin_amdgcn_ballot_w64(ge);
+            const unsigned long long mle = __builtin_amdgcn_ballot_w64(le);
             mvalid = mge | mle;
             inr = mge & mle;
             cge += __popcll(mge);
@@ -171,6 +208,11 @@ __device__ __forceinline__ void process(const float (&x)[NV], Lane &L, Wave &W,
             if (HIST == HIST_LDS) {
                 const int b = keep_or_minus1(cvt_flr_i32(u), inr);
                 atomicAdd((unsigned int *)((char *)H.lds + ((b << H.shift) + H.base)), 1u);
+            } else if (HIST == HIST_HOT) {
+                // Only in-range lanes off the hot bin touch LDS.
+                const int b = cvt_flr_i32(u);
+                const unsigned long long off_hot = __builtin_amdgcn_ballot_w64(b != H.hot);
+                lds_add1_masked((unsigned int)((b << H.shift) + H.base_abs), inr & off_hot);
             } else {
                 const int b = min(cvt_flr_i32(u), H.nbins - 1);
                 if ((inr >> (threadIdx.x & 63)) & 1ull) atomicAdd(&H.global[b], 1ull);
@@ -326,9 +368,11 @@ __device__ __forceinline__ void hist_setup(Hist &H, const HistRange &r, int nbin
 {
     const int lane = threadIdx.x & 63;
     const int C = 1 << copies_log2;
+    H.hot = -2;
     H.nbins = nbins;
     H.shift = copies_log2 + 2;
     H.base = (C + (lane & (C - 1))) * 4;
+    H.base_abs = (unsigned int)H.base + lds_offset(lds);
     H.lds = lds;
     H.global = acc;
     H.lo = r.lo;
@@ -358,6 +402,30 @@ __device__ __forceinline__ bool last_to_arrive(unsigned int *ticket, unsigned in
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const bool last = atomicAdd(ticket, 1u) == total - 1u;
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_shared = last ? 1u : 0u;
+    }
+    __syncthreads();
+    return *s_shared != 0u;
+}
+
+// The same election without the L2 write-back of the release fence, for a
+// block whose every write that the last block reads is an agent-scope atomic
+// store (written through the XCD's L2 to the device's point of coherence) or
+// an agent-scope atomic read-modify-write (performed there).  Each wavefront
+// waits for its own such writes to complete before the barrier, so all of
+// them are performed at device scope before thread 0 takes the ticket; the
+// last block then acquires (invalidates its L2) before it reads.  The release
+// fence's buffer_wbl2 would only add the write-back of plain stores, of
+// which there are none here; it stalls a block for several microseconds per
+// call, which the batched launch pays at every tile.
+__device__ __forceinline__ bool last_to_arrive_wt(unsigned int *ticket, unsigned int total,
+                                                  unsigned int *s_shared)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
         const bool last = atomicAdd(ticket, 1u) == total - 1u;
         if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_shared = last ? 1u : 0u;
@@ -439,7 +507,10 @@ __device__ __forceinline__ void scan_units(const Geom &g, long long u0, long lon
 
 // Local stage: reduce the lanes of the calling wavefront into one record
 // (written by lane 0).
-template <bool STATS, int ACC>
+// With WT (write-through) lane 0 writes the record as sixteen agent-scope
+// atomic stores, which gfx950 writes through its XCD's L2 (see
+// last_to_arrive_wt); otherwise as plain stores.
+template <bool STATS, int ACC, bool WT = false>
 __device__ __forceinline__ void write_wave_record(const Lane &L, const Wave &W, WaveRec *dst)
 {
     float mn = L.mn, mx = L.mx, s1h = L.s1, s1l = L.c1, s2h = L.s2, s2l = L.c2;
@@ -472,7 +543,15 @@ __device__ __forceinline__ void write_wave_record(const Lane &L, const Wave &W, 
         r.mx = mx;
         r.pad = 0.f;
         r.pad2 = 0ull;
-        *dst = r;
+        if (WT) {
+            const unsigned int *w = reinterpret_cast<const unsigned int *>(&r);
+            unsigned int *d = reinterpret_cast<unsigned int *>(dst);
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                __hip_atomic_store(d + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            *dst = r;
+        }
     }
 }
 
@@ -493,6 +572,66 @@ __device__ __forceinline__ void hist_flush(const unsigned int *lds, int nbins, i
             for (int c = 0; c < C; ++c) sum += lds[((nbins + 1) << copies_log2) + c];
         if (sum) atomicAdd(&acc[b], (unsigned long long)sum);
     }
+}
+
+// The hot bin of a block (HIST_HOT), chosen by its first wavefront before the
+// scan: the bin of the first in-range voxel among the first 64 of the block's
+// first work unit, computed with the same FP32 operations as every voxel's
+// bin (any value is correct; a likely one saves LDS atomics).  -2: none.
+__device__ __forceinline__ int hot_bin_pick(const Geom &g, long long u0, long long u1,
+                                            const Hist &H)
+{
+    if (u0 >= u1) return -2;
+    const int lane = threadIdx.x & 63;
+    const long long row = u0 / g.segs;
+    const long long sg = u0 - row * g.segs;
+    const long long y = row % g.ny, z = row / g.ny;
+    const long long c0 = sg * g.seg_len;
+    const long long len = min(g.seg_len, g.row_len - c0);
+    const float *q = g.ptr + y * g.sy + z * g.sz + c0;
+    const float v = lane < len ? q[lane] : qnan();
+    const int b = cvt_flr_i32(__fmul_rn(__fsub_rn(v, H.lo), H.scale));
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(v >= H.lo && v <= H.hi);
+    if (!m) return -2;
+    return __builtin_amdgcn_readlane(b, __builtin_ctzll(m));
+}
+
+// The flush of a hot-bin histogram: every other bin as in hist_flush, then
+// the hot bin's count, which is the block's in-range count (`s_inr`, summed
+// from the wavefronts' ballot counts) minus everything the block added to
+// LDS (`s_tot`, zeroed before the scan).  Starts with a barrier.
+__device__ __forceinline__ void hist_flush_hot(const unsigned int *lds, int nbins,
+                                               int copies_log2, unsigned long long *acc,
+                                               int hot, const unsigned int *s_inr,
+                                               unsigned int *s_tot)
+{
+    lds_wait();  // the masked LDS adds of this wavefront
+    __syncthreads();
+    const int C = 1 << copies_log2;
+    const int rot = threadIdx.x;
+    unsigned int mine = 0;
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+        unsigned int sum = 0;
+        for (int c = 0; c < C; ++c) sum += lds[((b + 1) << copies_log2) + ((c + rot) & (C - 1))];
+        if (b == nbins - 1)  // floor(u) == nbins belongs to the last bin
+            for (int c = 0; c < C; ++c) sum += lds[((nbins + 1) << copies_log2) + c];
+        mine += sum;
+        if (sum) atomicAdd(&acc[b], (unsigned long long)sum);
+    }
+    if (mine) atomicAdd(s_tot, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && hot >= 0) {
+        const unsigned int n_hot = *s_inr - *s_tot;
+        if (n_hot) atomicAdd(&acc[hot < nbins ? hot : nbins - 1], (unsigned long long)n_hot);
+    }
+}
+
+// The in-range count of the calling wavefront (ballots: x >= lo, x <= hi and
+// valid = either), added to the block's LDS counter by lane 0.
+__device__ __forceinline__ void add_in_range(const Wave &W, unsigned int *s_inr)
+{
+    if ((threadIdx.x & 63) == 0)
+        atomicAdd(s_inr, (unsigned int)(W.ge + W.le - W.valid));
 }
 
 // The [min, max] histogram range with its FP32 scale, formed from the data

@@ -415,6 +415,7 @@ void host_release()
         hipFree(w.d_range);
         hipHostFree(w.h_out);
         hipHostFree(w.h_counts);
+        release_ws(w.compute);  // the passes' workspace on the compute stream
         hipStreamDestroy(w.copy);
         hipStreamDestroy(w.compute);
         w.copy = w.compute = nullptr;

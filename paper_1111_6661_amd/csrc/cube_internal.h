@@ -40,7 +40,13 @@ struct Geom {
     uint64_t n_total;
 };
 
-enum : int32_t { HIST_NONE = 0, HIST_LDS = 1, HIST_GLOBAL = 2 };
+// Histogram modes of a pass: none; LDS sub-histograms (every in-range voxel
+// one LDS atomic); 64-bit global atomics (more bins than LDS holds); and LDS
+// sub-histograms with a hot bin: the block's most likely bin (the bin of the
+// first in-range voxel it meets) is never written to LDS -- its count is the
+// block's in-range count, known from the ballots, minus every other bin --
+// so a skewed histogram costs almost no LDS atomics.
+enum : int32_t { HIST_NONE = 0, HIST_LDS = 1, HIST_GLOBAL = 2, HIST_HOT = 3 };
 
 struct PassArgs {
     Geom g;
@@ -60,7 +66,8 @@ struct PassArgs {
 };
 
 // Kernel launchers (cube_kernels.hip).  `stats`: compute the statistics;
-// `hist`: HIST_NONE / HIST_LDS / HIST_GLOBAL.  Returns the launch error.
+// `hist`: HIST_NONE / HIST_LDS / HIST_GLOBAL / HIST_HOT.  Returns the launch
+// error.
 // `unroll`: float4 loads per lane per pipelined tile (2 or 4).
 hipError_t launch_pass(const PassArgs &a, bool stats, int hist, int threads,
                        int blocks, size_t lds_bytes, int unroll, hipStream_t s);
@@ -144,6 +151,9 @@ void cut_rows(Geom &g, long long blocks);
 int run_pass(const Box &b, bool stats, bool hist, int nbins, const HistRange &range,
              const HistRange *dev_range, cube_stats_t *dev_out, unsigned long long *dev_counts,
              bool accumulate, hipStream_t s);
+// Free the calling device's workspace of stream `s` (waits for its last
+// use); a library-owned stream releases it before hipStreamDestroy.
+void release_ws(hipStream_t s);
 // The empty-box results (n_total 0, NaN statistics, zero counts) on `s`.
 int write_empty(cube_stats_t *dev_out, unsigned long long *dev_counts, int nbins, hipStream_t s);
 
@@ -157,9 +167,34 @@ void quant_release();
 // A launch shape chosen by the autotuner (cube_tune.hip).
 struct TunedShape {
     int threads, unroll, copies, blocks_per_cu;
+    int hot;  // 1: the hot-bin histogram (HIST_HOT) instead of HIST_LDS
     float ms;
 };
+// The calling thread's hot-bin override for later single-box histogram
+// passes: -1 none (tuned or default), 0 HIST_LDS, 1 HIST_HOT.  The
+// autotuner sets it per candidate.
+void set_hot_override(int hot);
+int hot_override();
 // The tuned shape for (pass kind CUBE_Q_*, nbins, voxels), if any.
 bool tuned_shape(int kind, int nbins, uint64_t voxels, TunedShape *out);
+
+// The batched launch's automatic rule: threads per block, each query's tile
+// size from the query's own voxel count n (2^floor_log2, doubled while it is
+// below 2^cap_log2 and n needs more than 2^tiles_log2 tiles), and the LDS
+// budget of the histogram copies.  One rule serves every batch, so a query's
+// tiling (and with it the rounding of its moments) depends on the query
+// alone, never on the batch it is in.  cube_autotune_batch tunes it.
+struct BatchRule {
+    int threads, floor_log2, cap_log2, tiles_log2, lds_kib;
+    float ms;
+};
+constexpr BatchRule DEFAULT_BATCH_RULE = {512, 18, 20, 9, 64, 0.f};
+constexpr int CUBE_TUNE_BATCH = 4;  // the rule's "kind" in a saved tuning table
+bool batch_rule_ok(const BatchRule &r);
+// The tuned rule, if the table holds one; and the autotuner's store.
+bool tuned_batch_rule(BatchRule *out);
+void set_tuned_batch_rule(const BatchRule &r);
+// A query's tile size (voxels) under `r`.
+long long rule_tile_voxels(const BatchRule &r, unsigned long long n);
 
 }  // namespace cube

@@ -16,6 +16,8 @@ __global__ void __launch_bounds__(1024) k_pass(PassArgs a)
 {
     extern __shared__ unsigned int lds[];
     __shared__ unsigned int s_last;
+    __shared__ unsigned int s_inr, s_tot;  // HIST_HOT: in-range and LDS-counted voxels
+    __shared__ int s_hot;
     const int tid = threadIdx.x;
     const int wid = tid >> 6, nw = blockDim.x >> 6;
 
@@ -24,15 +26,28 @@ __global__ void __launch_bounds__(1024) k_pass(PassArgs a)
     const HistRange hr = HIST != HIST_NONE ? (a.dev_range ? *a.dev_range : a.range) : r0;
     const bool hist_on = HIST != HIST_NONE && hr.ok == 1;
     hist_setup(H, hr, a.nbins, a.copies_log2, lds, a.hist_acc);
-    if (HIST == HIST_LDS) lds_zero(lds, a.nbins, a.copies_log2);
-
-    Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    Wave W = {0.f, ACC == CUBE_ACCUM_NAIVE32 ? 1 : 0, 0ull, 0ull, 0ull};
 
     const Geom &g = a.g;
     const unsigned long long G = gridDim.x;
     const long long u0 = (long long)(((unsigned long long)g.n_units * blockIdx.x) / G);
     const long long u1 = (long long)(((unsigned long long)g.n_units * (blockIdx.x + 1)) / G);
+    if (HIST == HIST_HOT) {
+        // The hot bin and the two counters, published by lds_zero's barrier.
+        if (wid == 0) {
+            const int h = hist_on ? hot_bin_pick(g, u0, u1, H) : -2;
+            if (tid == 0) {
+                s_hot = h;
+                s_inr = 0u;
+                s_tot = 0u;
+            }
+        }
+    }
+    if (HIST == HIST_LDS || HIST == HIST_HOT) lds_zero(lds, a.nbins, a.copies_log2);
+    if (HIST == HIST_HOT) H.hot = s_hot;
+
+    Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    Wave W = {0.f, ACC == CUBE_ACCUM_NAIVE32 ? 1 : 0, 0ull, 0ull, 0ull};
+
     if (HIST == HIST_NONE || hist_on)
         scan_units<STATS, HIST, ACC, U>(g, u0, u1, L, W, H);
     else  // an invalid range bins nothing: count valid voxels only
@@ -40,6 +55,10 @@ __global__ void __launch_bounds__(1024) k_pass(PassArgs a)
 
     write_wave_record<STATS, ACC>(L, W, &a.recs[(long long)blockIdx.x * nw + wid]);
     if (HIST == HIST_LDS) hist_flush(lds, a.nbins, a.copies_log2, a.hist_acc);
+    if (HIST == HIST_HOT) {
+        if (hist_on) add_in_range(W, &s_inr);
+        hist_flush_hot(lds, a.nbins, a.copies_log2, a.hist_acc, H.hot, &s_inr, &s_tot);
+    }
 
     // Ticket: the last block to arrive performs the global stage.  One
     // release fence per block, not per thread: a fence in every thread costs
@@ -68,7 +87,8 @@ size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int thre
 {
     (void)stats;
     (void)threads;
-    if (hist == HIST_LDS) return (size_t)(nbins + 2) * ((size_t)1 << copies_log2) * 4u;
+    if (hist == HIST_LDS || hist == HIST_HOT)
+        return (size_t)(nbins + 2) * ((size_t)1 << copies_log2) * 4u;
     return 0;
 }
 
@@ -89,10 +109,14 @@ static const void *pick(bool stats, int hist, int acc, int u)
         if (hist == HIST_LDS)
             return naive ? kernel_of<true, HIST_LDS, CUBE_ACCUM_NAIVE32>(u)
                          : kernel_of<true, HIST_LDS, CUBE_ACCUM_FP64MERGE>(u);
+        if (hist == HIST_HOT)
+            return naive ? kernel_of<true, HIST_HOT, CUBE_ACCUM_NAIVE32>(u)
+                         : kernel_of<true, HIST_HOT, CUBE_ACCUM_FP64MERGE>(u);
         return naive ? kernel_of<true, HIST_GLOBAL, CUBE_ACCUM_NAIVE32>(u)
                      : kernel_of<true, HIST_GLOBAL, CUBE_ACCUM_FP64MERGE>(u);
     }
     if (hist == HIST_LDS) return kernel_of<false, HIST_LDS, CUBE_ACCUM_FP64MERGE>(u);
+    if (hist == HIST_HOT) return kernel_of<false, HIST_HOT, CUBE_ACCUM_FP64MERGE>(u);
     return kernel_of<false, HIST_GLOBAL, CUBE_ACCUM_FP64MERGE>(u);
 }
 

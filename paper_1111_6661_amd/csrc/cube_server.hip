@@ -416,7 +416,10 @@ void cube_server_destroy(cube_server_t *srv)
         if (sl.stream) hipStreamSynchronize(sl.stream);
         if (sl.batch) cube_batch_destroy(sl.batch);
         if (sl.done) hipEventDestroy(sl.done);
-        if (sl.stream) hipStreamDestroy(sl.stream);
+        if (sl.stream) {
+            release_ws(sl.stream);  // the plain mode's single-box workspace
+            hipStreamDestroy(sl.stream);
+        }
     }
     delete srv->policy;
     delete srv;

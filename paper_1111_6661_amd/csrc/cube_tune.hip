@@ -1,7 +1,8 @@
 // cube_tune.hip -- the autotuner of the single-box pass.
 //
 // It times candidate launch shapes (threads per block, float4 loads per
-// pipelined tile, LDS histogram copies, blocks per CU) of one pass kind on
+// pipelined tile, LDS histogram copies, blocks per CU, and for histograms the
+// plain or the hot-bin LDS form) of one pass kind on
 // the caller's own data with HIP events, and keeps the fastest shape per
 // (pass kind, histogram-size class, box-size class) in a table that the
 // launch planner consults when no explicit shape is set.  The table can be
@@ -33,6 +34,8 @@ struct TuneKey {
 
 std::mutex g_tmu;
 std::map<TuneKey, TunedShape> g_table;
+bool g_have_batch_rule = false;
+BatchRule g_batch_rule = DEFAULT_BATCH_RULE;
 
 int ilog2_ceil(uint64_t v)
 {
@@ -48,6 +51,28 @@ TuneKey key_of(int kind, int nbins, uint64_t voxels)
 }
 
 }  // namespace
+
+bool tuned_batch_rule(BatchRule *out)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_have_batch_rule) return false;
+    *out = g_batch_rule;
+    return true;
+}
+
+void set_tuned_batch_rule(const BatchRule &r)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_batch_rule = r;
+    g_have_batch_rule = true;
+}
+
+bool batch_rule_ok(const BatchRule &r)
+{
+    return (r.threads == 256 || r.threads == 512 || r.threads == 1024) && r.floor_log2 >= 12 &&
+           r.floor_log2 <= 30 && r.cap_log2 >= r.floor_log2 && r.cap_log2 <= 30 &&
+           r.tiles_log2 >= 0 && r.tiles_log2 <= 20 && r.lds_kib >= 16 && r.lds_kib <= 160;
+}
 
 bool tuned_shape(int kind, int nbins, uint64_t voxels, TunedShape *out)
 {
@@ -95,6 +120,7 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
         return hip_fail(e, "tune buffers");
     }
     const int cus = cu_count();
+    const int hot_c[] = {0, 1};
     const int threads_c[] = {256, 512, 1024};
     const int unroll_c[] = {2, 4};
     const int copies_c[] = {8, 16, 32};
@@ -116,13 +142,18 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
                                               (uint64_t *)d_counts, s);
         }
     };
+    const int prev_hot = hot_override();
     rc = CUBE_OK;
+    for (int hot : hot_c)
     for (int t : threads_c)
         for (int u : unroll_c)
             for (int c : copies_c) {
-                if (kind == CUBE_Q_STATS && c != copies_c[0]) continue;
-                // The LDS histogram must fit one block (160 KiB).
+                if (kind == CUBE_Q_STATS && (c != copies_c[0] || hot)) continue;
+                // The LDS histogram must fit one block (160 KiB); the hot-bin
+                // form exists for LDS histograms only.
                 if (kind != CUBE_Q_STATS && ((size_t)(nbins + 2) * c * 4 > 160 * 1024)) continue;
+                if (hot && nbins > 32768) continue;
+                set_hot_override(hot);
                 for (int bpc : bpc_c) {
                     const int blocks = std::min(cus * bpc, 4096);
                     if ((rc = cube_set_launch(t, blocks, kind == CUBE_Q_STATS ? 0 : c, u))) break;
@@ -142,6 +173,7 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
                     cd.sh.unroll = u;
                     cd.sh.copies = kind == CUBE_Q_STATS ? 0 : c;
                     cd.sh.blocks_per_cu = bpc;
+                    cd.sh.hot = hot;
                     cd.sh.ms = ms / reps;
                     cd.ms = ms / reps;
                     cands.push_back(cd);
@@ -149,7 +181,9 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
                 if (rc) break;
             }
     cube_set_launch(prev_t, prev_b, prev_c, prev_u);
+    set_hot_override(prev_hot);
     hipStreamSynchronize(s);
+    release_ws(s);  // before the stream goes: its workspace is keyed by it
     hipFree(d_out);
     hipFree(d_counts);
     hipEventDestroy(e0);
@@ -168,8 +202,8 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
         auto fmt = [&](const TunedShape &sh) {
             snprintf(buf, sizeof buf,
                      "{\"threads\": %d, \"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, "
-                     "\"ms\": %.5f}",
-                     sh.threads, sh.unroll, sh.copies, sh.blocks_per_cu, sh.ms);
+                     "\"hot\": %d, \"ms\": %.5f}",
+                     sh.threads, sh.unroll, sh.copies, sh.blocks_per_cu, sh.hot, sh.ms);
             return std::string(buf);
         };
         rep += fmt(cands[0].sh) + ", \"worst\": " + fmt(cands.back().sh);
@@ -190,13 +224,24 @@ int cube_tune_save(const char *path)
     std::lock_guard<std::mutex> lk(g_tmu);
     fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [");
     bool first = true;
+    if (g_have_batch_rule) {
+        // The batched launch's rule (one per table).
+        fprintf(f,
+                "\n  {\"kind\": %d, \"batch_threads\": %d, \"floor_log2\": %d, "
+                "\"cap_log2\": %d, \"tiles_log2\": %d, \"lds_kib\": %d, \"ms\": %.5f}",
+                CUBE_TUNE_BATCH, g_batch_rule.threads, g_batch_rule.floor_log2,
+                g_batch_rule.cap_log2, g_batch_rule.tiles_log2, g_batch_rule.lds_kib,
+                g_batch_rule.ms);
+        first = false;
+    }
     for (auto &kv : g_table) {
         fprintf(f,
                 "%s\n  {\"kind\": %d, \"bins_log2\": %d, \"size_log2\": %d, \"threads\": %d, "
-                "\"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, \"ms\": %.5f}",
+                "\"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, \"ms\": %.5f, "
+                "\"hot\": %d}",
                 first ? "" : ",", kv.first.kind, kv.first.bins_log2, kv.first.size_log2,
                 kv.second.threads, kv.second.unroll, kv.second.copies, kv.second.blocks_per_cu,
-                kv.second.ms);
+                kv.second.ms, kv.second.hot);
         first = false;
     }
     fprintf(f, "\n]}\n");
@@ -216,16 +261,42 @@ int cube_tune_load(const char *path)
     int n = 0;
     bool arch_ok = false;
     std::map<TuneKey, TunedShape> t;
+    bool have_rule = false;
+    BatchRule rule = DEFAULT_BATCH_RULE;
     while (fgets(line, sizeof line, f)) {
         if (strstr(line, "\"arch\": \"gfx950\"")) arch_ok = true;
-        int kind, bl, sl, th, un, co, bp;
+        const char *brace = strchr(line, '{');
+        int bk;
+        double bms;
+        BatchRule r;
+        if (brace && sscanf(brace,
+                            "{\"kind\": %d, \"batch_threads\": %d, \"floor_log2\": %d, "
+                            "\"cap_log2\": %d, \"tiles_log2\": %d, \"lds_kib\": %d, "
+                            "\"ms\": %lf}",
+                            &bk, &r.threads, &r.floor_log2, &r.cap_log2, &r.tiles_log2,
+                            &r.lds_kib, &bms) == 7) {
+            if (bk != CUBE_TUNE_BATCH || !batch_rule_ok(r)) {
+                fclose(f);
+                return fail(CUBE_EINVAL, "%s: bad batch rule", path);
+            }
+            r.ms = (float)bms;
+            rule = r;
+            have_rule = true;
+            ++n;
+            continue;
+        }
+        int kind, bl, sl, th, un, co, bp, hot = 0;
         double ms;
-        if (sscanf(strchr(line, '{') ? strchr(line, '{') : line,
-                   "{\"kind\": %d, \"bins_log2\": %d, \"size_log2\": %d, \"threads\": %d, "
-                   "\"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, \"ms\": %lf}",
-                   &kind, &bl, &sl, &th, &un, &co, &bp, &ms) == 8) {
+        // "hot" is optional (tables written before the hot-bin form have none).
+        const int got = sscanf(strchr(line, '{') ? strchr(line, '{') : line,
+                               "{\"kind\": %d, \"bins_log2\": %d, \"size_log2\": %d, "
+                               "\"threads\": %d, \"unroll\": %d, \"copies\": %d, "
+                               "\"blocks_per_cu\": %d, \"ms\": %lf, \"hot\": %d}",
+                               &kind, &bl, &sl, &th, &un, &co, &bp, &ms, &hot);
+        if (got == 8 || got == 9) {
             if ((th != 256 && th != 512 && th != 1024) || (un != 2 && un != 4) ||
-                co < 0 || co > 32 || (co & (co - 1)) || bp < 1 || bp > 64) {
+                co < 0 || co > 32 || (co & (co - 1)) || bp < 1 || bp > 64 ||
+                (hot != 0 && hot != 1)) {
                 fclose(f);
                 return fail(CUBE_EINVAL, "%s: bad entry", path);
             }
@@ -234,6 +305,7 @@ int cube_tune_load(const char *path)
             sh.unroll = un;
             sh.copies = co;
             sh.blocks_per_cu = bp;
+            sh.hot = hot;
             sh.ms = (float)ms;
             t[TuneKey{kind, bl, sl}] = sh;
             ++n;
@@ -243,6 +315,10 @@ int cube_tune_load(const char *path)
     if (!arch_ok) return fail(CUBE_EINVAL, "%s: not a gfx950 tuning table", path);
     std::lock_guard<std::mutex> lk(g_tmu);
     for (auto &kv : t) g_table[kv.first] = kv.second;
+    if (have_rule) {
+        g_batch_rule = rule;
+        g_have_batch_rule = true;
+    }
     return n;
     CUBE_GUARD_END
 }
@@ -252,6 +328,8 @@ void cube_tune_clear(void)
     CUBE_GUARD_BEGIN
     std::lock_guard<std::mutex> lk(g_tmu);
     g_table.clear();
+    g_have_batch_rule = false;
+    g_batch_rule = DEFAULT_BATCH_RULE;
     CUBE_GUARD_VOID_END
 }
 

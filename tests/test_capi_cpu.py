@@ -105,6 +105,11 @@ def test_mode_and_launch_setters_validate():
     prev = cs.cube_set_accum_mode(cs.CUBE_ACCUM_KAHAN32)
     assert cs.cube_set_accum_mode(prev) == cs.CUBE_ACCUM_KAHAN32
     cs.cube_set_launch(0, 0, 0, 0)
+    assert _code(cs.cube_set_hist_mode, 3)[0] == cs.CUBE_EINVAL
+    assert _code(cs.cube_set_hist_mode, -1)[0] == cs.CUBE_EINVAL
+    assert cs.cube_set_hist_mode(cs.CUBE_HIST_HOT) == cs.CUBE_HIST_AUTO
+    assert cs.cube_set_hist_mode(cs.CUBE_HIST_PLAIN) == cs.CUBE_HIST_HOT
+    assert cs.cube_set_hist_mode(cs.CUBE_HIST_AUTO) == cs.CUBE_HIST_PLAIN
 
 
 def test_mode_is_per_thread():
@@ -159,6 +164,37 @@ def test_tuning_table_round_trip(tmp_path):
             cs.cube_tune_load(str(bad_entry))
         with pytest.raises(cs.CubeError):
             cs.cube_tune_load(str(tmp_path / "missing.json"))
+        # the optional hot-bin field: 0 or 1 round-trips, anything else is refused
+        hot = tmp_path / "hot.json"
+        hot.write_text('{"arch": "gfx950", "entries": [\n  {"kind": 2, "bins_log2": 12, '
+                       '"size_log2": 35, "threads": 1024, "unroll": 4, "copies": 8, '
+                       '"blocks_per_cu": 2, "ms": 1.0, "hot": 1}\n]}\n')
+        cs.cube_tune_clear()
+        assert cs.cube_tune_load(str(hot)) == 1
+        cs.cube_tune_save(str(out))
+        assert '"hot": 1' in open(out).read()
+        # the batched launch's rule: one line, round-trips, bad values refused
+        rule = tmp_path / "rule.json"
+        rule.write_text('{"arch": "gfx950", "entries": [\n  {"kind": 4, "batch_threads": 256, '
+                        '"floor_log2": 17, "cap_log2": 20, "tiles_log2": 10, "lds_kib": 128, '
+                        '"ms": 0.25}\n]}\n')
+        cs.cube_tune_clear()
+        assert cs.cube_tune_load(str(rule)) == 1
+        cs.cube_tune_save(str(out))
+        assert '"batch_threads": 256, "floor_log2": 17, "cap_log2": 20, "tiles_log2": 10, ' \
+               '"lds_kib": 128' in open(out).read()
+        for bad in ('"batch_threads": 300', '"cap_log2": 16', '"lds_kib": 200'):
+            key = bad.split(":")[0]
+            txt = open(rule).read()
+            i = txt.index(key)
+            j = txt.index(",", i)
+            (tmp_path / "badrule.json").write_text(txt[:i] + bad + txt[j:])
+            with pytest.raises(cs.CubeError):
+                cs.cube_tune_load(str(tmp_path / "badrule.json"))
+        bad_hot = tmp_path / "badhot.json"
+        bad_hot.write_text(open(hot).read().replace('"hot": 1', '"hot": 2'))
+        with pytest.raises(cs.CubeError):
+            cs.cube_tune_load(str(bad_hot))
     finally:
         cs.cube_tune_clear()
 

@@ -144,6 +144,49 @@ def test_automatic_tile_sizes(cs):
     torch.cuda.empty_cache()
 
 
+def test_tuned_batch_rule(cs, tmp_path):
+    """The batch autotuner picks a rule on a mixed batch; later batches with
+    automatic tile and threads run it: every query agrees with the oracle and
+    gives the same bits alone and in the mix; the rule survives a save and a
+    load of the tuning table."""
+    items = make_items(seed=13, n=10)
+    kinds = [cs.CUBE_Q_MINMAX, cs.CUBE_Q_FUSED, cs.CUBE_Q_STATS, cs.CUBE_Q_HIST]
+    nbins_list = [512, 100, 1, 4096]
+    mix = Outputs(len(items), 4096)
+    qs = queries_for(cs, items, mix, kinds, nbins_list)
+    cs.cube_tune_clear()
+    try:
+        rep = cs.cube_autotune_batch(qs, reps=2)
+        best = rep["best"]
+        assert best["threads"] in (256, 512, 1024) and rep["candidates"] == 162
+        assert 16 <= best["floor_log2"] <= best["cap_log2"] <= 21
+        mix.out.zero_()
+        mix.cnt.zero_()
+        b = cs.Batch(tile_voxels=0, threads=0)
+        b.enqueue(qs)
+        b.check()
+        for i, t in enumerate(items):
+            check_query(cs, mix, i, t, kinds[i % 4], nbins_list[i % 4])
+            alone = Outputs(1, 4096)
+            b2 = cs.Batch(tile_voxels=0, threads=0)
+            b2.enqueue(queries_for(cs, [t], alone, [kinds[i % 4]], [nbins_list[i % 4]]))
+            b2.check()
+            b2.close()
+            assert torch.equal(alone.out[0], mix.out[i]), f"item {i} stats differ alone vs mix"
+            assert torch.equal(alone.cnt[0], mix.cnt[i]), f"item {i} counts differ alone vs mix"
+        b.close()
+        path = tmp_path / "t.json"
+        cs.cube_tune_save(str(path))
+        line = [l for l in open(path) if "batch_threads" in l]
+        assert len(line) == 1 and f'"batch_threads": {best["threads"]}' in line[0]
+        cs.cube_tune_clear()
+        assert cs.cube_tune_load(str(path)) == 1
+        cs.cube_tune_save(str(tmp_path / "u.json"))
+        assert [l for l in open(tmp_path / "u.json") if "batch_threads" in l] == line
+    finally:
+        cs.cube_tune_clear()
+
+
 def test_batch_of_workload_items(cs):
     """The whole 64-item workload (uneven sizes, 1.6e8 voxels), two-pass 512
     bins each, in the form the benchmark times (a graph replay with the
