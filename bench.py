@@ -514,9 +514,10 @@ def main() -> int:
                     help="threads,blocks,hist_copies,unroll override (0 = automatic)")
     ap.add_argument("--only-fused", action="store_true",
                     help="time the fused pass only (for profiler runs)")
-    ap.add_argument("--tune", choices=("table", "run", "off"), default="table",
+    ap.add_argument("--tune", choices=("table", "run", "batch", "off"), default="table",
                     help="launch shapes: the shipped tuning table (autotune if it is "
-                         "missing), a fresh autotune, or the planner's defaults")
+                         "missing), a fresh autotune of every class, the table with a fresh "
+                         "autotune of the batched launch's rule only, or the planner's defaults")
     ap.add_argument("--tune-save", default="", help="save the tuning table to this path")
     ap.add_argument("--no-tune", action="store_true", help="same as --tune off")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-item batch")
@@ -571,7 +572,7 @@ def main() -> int:
     tuned = None
     mode = "off" if (args.no_tune or args.launch) else args.tune
     table = os.path.join(ROOT, TUNE_TABLE)
-    if mode == "table" and os.path.exists(table):
+    if mode in ("table", "batch") and os.path.exists(table):
         tuned = {"source": TUNE_TABLE, "entries": cs.cube_tune_load(table)}
         log(f"tuning table {TUNE_TABLE}: {tuned['entries']} entries")
     elif mode != "off":
@@ -649,7 +650,7 @@ def main() -> int:
     if not args.only_fused and not args.no_batch:
         log("batch64 ...")
         extra["batch64"] = bench_batch64(cs, synth, torch, dev, max(10, args.steps // 2),
-                                         tune=mode == "run")
+                                         tune=mode in ("run", "batch"))
         log(f"batch64: graph {extra['batch64']['batched_graph_ms']:.3f} ms vs plain "
             f"{extra['batch64']['plain_ms']:.3f} ms")
     if not args.only_fused and not args.no_select:

@@ -84,15 +84,15 @@ struct BatchArgs {
 
 constexpr unsigned int DONE_FAILED = 0x80000000u;
 
-constexpr int BATCH_UNROLL = 4;
-
-template <bool STATS, int HIST>
+template <bool STATS, int HIST, int U>
 __device__ void batch_scan(const BatchItem &it, long long u0, long long u1, Lane &L, Wave &W,
                            const Hist &H)
 {
-    scan_units<STATS, HIST, CUBE_ACCUM_FP64MERGE, BATCH_UNROLL>(it.g, u0, u1, L, W, H);
+    scan_units<STATS, HIST, CUBE_ACCUM_FP64MERGE, U>(it.g, u0, u1, L, W, H);
 }
 
+// U: float4 loads per lane per pipelined tile step (2 or 4, the rule's).
+template <int U>
 __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
 {
     extern __shared__ unsigned int lds[];
@@ -169,13 +169,13 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         if (hist) lds_zero(lds, it.nbins, a.copies_log2);
         if (!skip) {
             if (stats && hist_on)
-                batch_scan<true, HIST_LDS>(it, u0, u1, L, W, H);
+                batch_scan<true, HIST_LDS, U>(it, u0, u1, L, W, H);
             else if (stats)
-                batch_scan<true, HIST_NONE>(it, u0, u1, L, W, H);
+                batch_scan<true, HIST_NONE, U>(it, u0, u1, L, W, H);
             else if (hist_on)
-                batch_scan<false, HIST_LDS>(it, u0, u1, L, W, H);
+                batch_scan<false, HIST_LDS, U>(it, u0, u1, L, W, H);
             else  // an invalid [min, max] range bins nothing
-                batch_scan<false, HIST_NONE>(it, u0, u1, L, W, H);
+                batch_scan<false, HIST_NONE, U>(it, u0, u1, L, W, H);
         }
         const long long rec0 = tile.phase == 1 ? it.rec1 : it.rec2;
         WaveRec *recs = a.recs + rec0;
@@ -262,9 +262,15 @@ long long rule_tile_voxels(const BatchRule &r, unsigned long long n)
     return tv;
 }
 
-static hipError_t batch_occupancy(int threads, size_t lds, int *bpc)
+static const void *batch_kernel(int unroll)
 {
-    const void *k = reinterpret_cast<const void *>(&k_batch);
+    return unroll == 2 ? reinterpret_cast<const void *>(&k_batch<2>)
+                       : reinterpret_cast<const void *>(&k_batch<4>);
+}
+
+static hipError_t batch_occupancy(int threads, int unroll, size_t lds, int *bpc)
+{
+    const void *k = batch_kernel(unroll);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -305,6 +311,7 @@ struct cube_batch {
     BatchArgs args;
     int threads_req = 0;             // 0: the rule's
     int threads = 512, blocks = 0;   // of the current work list
+    int unroll = 4;                  // of the current work list (the rule's)
     size_t lds = 0;
     long long tile_voxels = 1 << 20; // 0: the rule's, per query
     bool have_rule = false;          // the autotuner's candidate, else the table's
@@ -442,8 +449,8 @@ int launch_batch(cube_batch *b, hipStream_t s)
     void *args[] = {&a};
     hipError_t e = order_after_previous(b, s);
     if (e != hipSuccess) return hip_fail(e, "batch ordering");
-    e = hipLaunchKernel(reinterpret_cast<const void *>(&k_batch), dim3(b->blocks),
-                        dim3(b->threads), args, b->lds, s);
+    e = hipLaunchKernel(batch_kernel(b->unroll), dim3(b->blocks), dim3(b->threads), args,
+                        b->lds, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     if ((e = mark_launched(b, s)) != hipSuccess) return hip_fail(e, "batch event");
     return CUBE_OK;
@@ -517,6 +524,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     else
         tuned_batch_rule(&rule);
     b->threads = b->threads_req ? b->threads_req : rule.threads;
+    b->unroll = rule.unroll;
     const int nw = b->threads / 64;
     for (int i = 0; i < n; ++i) {
         const cube_query_t &qq = q[i];
@@ -633,7 +641,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     while (clog < 5 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= lds_budget) ++clog;
     b->lds = ((size_t)(max_bins + 2) << clog) * 4;
     int bpc = 1;
-    if ((e = batch_occupancy(b->threads, b->lds, &bpc)) != hipSuccess)
+    if ((e = batch_occupancy(b->threads, b->unroll, b->lds, &bpc)) != hipSuccess)
         return hip_fail(e, "batch occupancy");
     if (bpc < 1) bpc = 1;
     long long blocks = (long long)cu_count() * bpc;
@@ -709,8 +717,8 @@ int cube_batch_graph_launch(cube_batch_t *b, void *stream)
         }
         BatchArgs a = b->args;
         void *args[] = {&a};
-        e = hipLaunchKernel(reinterpret_cast<const void *>(&k_batch), dim3(b->blocks),
-                            dim3(b->threads), args, b->lds, cap);
+        e = hipLaunchKernel(batch_kernel(b->unroll), dim3(b->blocks), dim3(b->threads), args,
+                            b->lds, cap);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &g);
         hipStreamDestroy(cap);
@@ -775,10 +783,12 @@ int cube_autotune_batch(const cube_query_t *q, int32_t n, int32_t reps, char *re
     int rc = cube_batch_create(&b);
     std::vector<BatchRule> cands;
     for (int th : {256, 512, 1024})
-        for (int fl : {16, 17, 18})
-            for (int cp : {19, 20, 21})
-                for (int tl : {8, 9, 10})
-                    for (int kib : {64, 128}) cands.push_back(BatchRule{th, fl, cp, tl, kib, 0.f});
+        for (int un : {2, 4})
+            for (int fl : {16, 17, 18})
+                for (int cp : {19, 20, 21})
+                    for (int tl : {8, 9, 10})
+                        for (int kib : {64, 128})
+                            cands.push_back(BatchRule{th, un, fl, cp, tl, kib, 0.f});
     BatchRule best = DEFAULT_BATCH_RULE, worst = DEFAULT_BATCH_RULE;
     best.ms = 1e30f;
     worst.ms = -1.f;
@@ -818,9 +828,10 @@ int cube_autotune_batch(const cube_query_t *q, int32_t n, int32_t reps, char *re
         char buf[512];
         auto fmt = [](const BatchRule &r, char *out, size_t cap) {
             snprintf(out, cap,
-                     "{\"threads\": %d, \"floor_log2\": %d, \"cap_log2\": %d, "
+                     "{\"threads\": %d, \"unroll\": %d, \"floor_log2\": %d, \"cap_log2\": %d, "
                      "\"tiles_log2\": %d, \"lds_kib\": %d, \"ms\": %.5f}",
-                     r.threads, r.floor_log2, r.cap_log2, r.tiles_log2, r.lds_kib, r.ms);
+                     r.threads, r.unroll, r.floor_log2, r.cap_log2, r.tiles_log2, r.lds_kib,
+                     r.ms);
         };
         char sb[200], sw[200];
         fmt(best, sb, sizeof sb);

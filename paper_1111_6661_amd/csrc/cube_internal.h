@@ -178,17 +178,18 @@ int hot_override();
 // The tuned shape for (pass kind CUBE_Q_*, nbins, voxels), if any.
 bool tuned_shape(int kind, int nbins, uint64_t voxels, TunedShape *out);
 
-// The batched launch's automatic rule: threads per block, each query's tile
+// The batched launch's automatic rule: threads per block, float4 loads per
+// lane per pipelined step, each query's tile
 // size from the query's own voxel count n (2^floor_log2, doubled while it is
 // below 2^cap_log2 and n needs more than 2^tiles_log2 tiles), and the LDS
 // budget of the histogram copies.  One rule serves every batch, so a query's
 // tiling (and with it the rounding of its moments) depends on the query
 // alone, never on the batch it is in.  cube_autotune_batch tunes it.
 struct BatchRule {
-    int threads, floor_log2, cap_log2, tiles_log2, lds_kib;
+    int threads, unroll, floor_log2, cap_log2, tiles_log2, lds_kib;
     float ms;
 };
-constexpr BatchRule DEFAULT_BATCH_RULE = {512, 18, 20, 9, 64, 0.f};
+constexpr BatchRule DEFAULT_BATCH_RULE = {512, 4, 18, 20, 9, 64, 0.f};
 constexpr int CUBE_TUNE_BATCH = 4;  // the rule's "kind" in a saved tuning table
 bool batch_rule_ok(const BatchRule &r);
 // The tuned rule, if the table holds one; and the autotuner's store.

@@ -69,7 +69,8 @@ void set_tuned_batch_rule(const BatchRule &r)
 
 bool batch_rule_ok(const BatchRule &r)
 {
-    return (r.threads == 256 || r.threads == 512 || r.threads == 1024) && r.floor_log2 >= 12 &&
+    return (r.threads == 256 || r.threads == 512 || r.threads == 1024) &&
+           (r.unroll == 2 || r.unroll == 4) && r.floor_log2 >= 12 &&
            r.floor_log2 <= 30 && r.cap_log2 >= r.floor_log2 && r.cap_log2 <= 30 &&
            r.tiles_log2 >= 0 && r.tiles_log2 <= 20 && r.lds_kib >= 16 && r.lds_kib <= 160;
 }
@@ -227,9 +228,9 @@ int cube_tune_save(const char *path)
     if (g_have_batch_rule) {
         // The batched launch's rule (one per table).
         fprintf(f,
-                "\n  {\"kind\": %d, \"batch_threads\": %d, \"floor_log2\": %d, "
+                "\n  {\"kind\": %d, \"batch_threads\": %d, \"unroll\": %d, \"floor_log2\": %d, "
                 "\"cap_log2\": %d, \"tiles_log2\": %d, \"lds_kib\": %d, \"ms\": %.5f}",
-                CUBE_TUNE_BATCH, g_batch_rule.threads, g_batch_rule.floor_log2,
+                CUBE_TUNE_BATCH, g_batch_rule.threads, g_batch_rule.unroll, g_batch_rule.floor_log2,
                 g_batch_rule.cap_log2, g_batch_rule.tiles_log2, g_batch_rule.lds_kib,
                 g_batch_rule.ms);
         first = false;
@@ -270,11 +271,11 @@ int cube_tune_load(const char *path)
         double bms;
         BatchRule r;
         if (brace && sscanf(brace,
-                            "{\"kind\": %d, \"batch_threads\": %d, \"floor_log2\": %d, "
-                            "\"cap_log2\": %d, \"tiles_log2\": %d, \"lds_kib\": %d, "
-                            "\"ms\": %lf}",
-                            &bk, &r.threads, &r.floor_log2, &r.cap_log2, &r.tiles_log2,
-                            &r.lds_kib, &bms) == 7) {
+                            "{\"kind\": %d, \"batch_threads\": %d, \"unroll\": %d, "
+                            "\"floor_log2\": %d, \"cap_log2\": %d, \"tiles_log2\": %d, "
+                            "\"lds_kib\": %d, \"ms\": %lf}",
+                            &bk, &r.threads, &r.unroll, &r.floor_log2, &r.cap_log2,
+                            &r.tiles_log2, &r.lds_kib, &bms) == 8) {
             if (bk != CUBE_TUNE_BATCH || !batch_rule_ok(r)) {
                 fclose(f);
                 return fail(CUBE_EINVAL, "%s: bad batch rule", path);

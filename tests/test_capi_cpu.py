@@ -176,14 +176,14 @@ def test_tuning_table_round_trip(tmp_path):
         # the batched launch's rule: one line, round-trips, bad values refused
         rule = tmp_path / "rule.json"
         rule.write_text('{"arch": "gfx950", "entries": [\n  {"kind": 4, "batch_threads": 256, '
-                        '"floor_log2": 17, "cap_log2": 20, "tiles_log2": 10, "lds_kib": 128, '
+                        '"unroll": 2, "floor_log2": 17, "cap_log2": 20, "tiles_log2": 10, "lds_kib": 128, '
                         '"ms": 0.25}\n]}\n')
         cs.cube_tune_clear()
         assert cs.cube_tune_load(str(rule)) == 1
         cs.cube_tune_save(str(out))
-        assert '"batch_threads": 256, "floor_log2": 17, "cap_log2": 20, "tiles_log2": 10, ' \
+        assert '"batch_threads": 256, "unroll": 2, "floor_log2": 17, "cap_log2": 20, "tiles_log2": 10, ' \
                '"lds_kib": 128' in open(out).read()
-        for bad in ('"batch_threads": 300', '"cap_log2": 16', '"lds_kib": 200'):
+        for bad in ('"batch_threads": 300', '"unroll": 3', '"cap_log2": 16', '"lds_kib": 200'):
             key = bad.split(":")[0]
             txt = open(rule).read()
             i = txt.index(key)
