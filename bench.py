@@ -519,6 +519,8 @@ def main() -> int:
                          "missing), a fresh autotune of every class, the table with a fresh "
                          "autotune of the batched launch's rule only, or the planner's defaults")
     ap.add_argument("--tune-save", default="", help="save the tuning table to this path")
+    ap.add_argument("--tune-table", default="",
+                    help="tuning table to load instead of the shipped one")
     ap.add_argument("--no-tune", action="store_true", help="same as --tune off")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-item batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -571,9 +573,9 @@ def main() -> int:
 
     tuned = None
     mode = "off" if (args.no_tune or args.launch) else args.tune
-    table = os.path.join(ROOT, TUNE_TABLE)
+    table = args.tune_table or os.path.join(ROOT, TUNE_TABLE)
     if mode in ("table", "batch") and os.path.exists(table):
-        tuned = {"source": TUNE_TABLE, "entries": cs.cube_tune_load(table)}
+        tuned = {"source": args.tune_table or TUNE_TABLE, "entries": cs.cube_tune_load(table)}
         log(f"tuning table {TUNE_TABLE}: {tuned['entries']} entries")
     elif mode != "off":
         tuned = {"source": "autotune"}

@@ -417,7 +417,8 @@ CUBE_API int cube_batch_run(const cube_query_t *q, int32_t n);
 
 /*
  * Autotuner of the batched launch.  Times candidate automatic rules -- threads
- * per block (256, 512, 1024), float4 loads per lane per pipelined step (2
+ * per block (256 or 512: 1024-thread blocks leave no room on a CU for a
+ * concurrent batch), float4 loads per lane per pipelined step (2
  * or 4), each query's tile size as a function of its
  * own voxel count (a floor of 2^16..2^18 voxels, doubled up to a cap of
  * 2^19..2^21 while the query needs more than 2^8..2^10 tiles) and the LDS

@@ -109,19 +109,23 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
     __syncthreads();
     const unsigned int tag = s_tag;
 
-    // Tiles are claimed one ahead: thread 0 takes the next tile's index as
-    // the current one starts, so the claim's round trip overlaps the scan.
-    // A claimed first-phase tile is always held by a block working on an
-    // earlier first-phase tile (every first-phase tile precedes every
-    // second-phase tile in the list), which never waits, so every first-phase
-    // tile is still processed and second-phase waits end.
+    // While more than two grids' worth of tiles lie beyond the current one,
+    // thread 0 claims the next tile as the current one starts, so the
+    // claim's round trip overlaps the scan; nearer the end of the list it
+    // claims after the tile, so that a block never holds a tile that an idle
+    // block could be working on (a short batch would otherwise run on half
+    // its blocks, two tiles each).  A claimed first-phase tile is always held
+    // by a block working on an earlier first-phase tile (every first-phase
+    // tile precedes every second-phase tile in the list), which never waits,
+    // so every first-phase tile is still processed and second-phase waits end.
     if (tid == 0) s_tile = (int)atomicAdd(&a.ctl[0], 1u);
     __syncthreads();
     while (true) {
         const int t = s_tile;
         if (t >= a.n_tiles) break;
+        const bool early = (long long)t + 2ll * gridDim.x < (long long)a.n_tiles;
         unsigned int next = 0u;
-        if (tid == 0) next = atomicAdd(&a.ctl[0], 1u);
+        if (tid == 0 && early) next = atomicAdd(&a.ctl[0], 1u);
         const BatchTile tile = a.tiles[t];
         const BatchItem &it = a.items[tile.item];
         BatchState *st = &a.state[tile.item];
@@ -239,7 +243,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                 }
             }
         }
-        if (tid == 0) s_tile = (int)next;
+        if (tid == 0) s_tile = (int)(early ? next : atomicAdd(&a.ctl[0], 1u));
         __syncthreads();
     }
 
@@ -781,8 +785,12 @@ int cube_autotune_batch(const cube_query_t *q, int32_t n, int32_t reps, char *re
     }
     cube_batch_t *b = nullptr;
     int rc = cube_batch_create(&b);
+    // Block sizes 256 and 512 only: a 1024-thread block fills all of a CU's
+    // wavefront slots, so the concurrent batches of a server (one per slot
+    // stream) could no longer share CUs -- it won a lone batch by 10 % and
+    // lost the served p50 by 70 % (5.3 -> 9.0 ms on the serving mix).
     std::vector<BatchRule> cands;
-    for (int th : {256, 512, 1024})
+    for (int th : {256, 512})
         for (int un : {2, 4})
             for (int fl : {16, 17, 18})
                 for (int cp : {19, 20, 21})

@@ -158,7 +158,7 @@ def test_tuned_batch_rule(cs, tmp_path):
     try:
         rep = cs.cube_autotune_batch(qs, reps=2)
         best = rep["best"]
-        assert best["threads"] in (256, 512, 1024) and rep["candidates"] == 324
+        assert best["threads"] in (256, 512) and rep["candidates"] == 216
         assert best["unroll"] in (2, 4)
         assert 16 <= best["floor_log2"] <= best["cap_log2"] <= 21
         mix.out.zero_()
