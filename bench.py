@@ -267,6 +267,7 @@ def bench_stress(cs, synth, torch, dev, steps: int, tune: bool = False):
                                                            cnt.data_ptr(), sp),
                           stream, steps, 2)
     c = cnt.cpu().numpy()
+    plan = cs.cube_describe_plan(ptr, dims, cs.CUBE_Q_FUSED, nb)
     ref = modes["fp64merge"]
     orc = stress_oracle_reference(synth)
     vs_oracle = None
@@ -280,7 +281,7 @@ def bench_stress(cs, synth, torch, dev, steps: int, tune: bool = False):
     return {"voxels": r.n, "nbins": nb, "fused_ms": ms, "voxels_per_s": r.n / (ms * 1e-3),
             "rel_err_vs_oracle": vs_oracle,
             "oracle_reference": STRESS_ORACLE if vs_oracle is not None else None,
-            "autotune": tuned,
+            "autotune": tuned, "fused_plan": plan,
             "pct_hbm_peak": 100.0 * 4 * r.n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bin0_fraction_of_valid": float(c[0]) / max(1, st.n_valid),
             "counts_sum_equals_n_total": int(c.sum()) == r.n,
@@ -631,7 +632,8 @@ def main() -> int:
         "nan_equals_stats_pass": int(c[nbins + 2]) == st0.n_nan == st.n_nan,
     }
 
-    extra = {}
+    extra = {"fused_plan": cs.cube_describe_plan(ptr, dims, cs.CUBE_Q_FUSED, nbins)}
+    log(f"fused plan: {extra['fused_plan']}")
     n_short = max(5, args.steps // 2)
     _, probe_ms = time_launches(read_probe, stream, n_short, 2)
     probe_gbs = 4 * r.n / (probe_ms * 1e-3) / 1e9

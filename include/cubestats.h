@@ -171,7 +171,9 @@ CUBE_API int cube_stats_hist_minmax_async(const float *ptr, const int64_t *dims,
  * streams, or threads without ordering) race on that array and must not be
  * made.  The launch grid is narrowed to CUBE_NOALLOC_MAX_RECORDS wave
  * records (1024 blocks of 1024 threads); an explicit cube_set_launch shape
- * needing more is rejected with CUBE_EINVAL.
+ * needing more is rejected with CUBE_EINVAL.  Under a dynamic partition
+ * (cube_set_partition) the records are one per chunk: a plan with more
+ * chunks is cut into CUBE_NOALLOC_MAX_RECORDS larger ones.
  */
 #define CUBE_NOALLOC_MAX_RECORDS 16384
 CUBE_API int cube_stats_hist_noalloc(const float *ptr, const int64_t *dims, float lo, float hi,
@@ -197,7 +199,8 @@ CUBE_API int cube_set_accum_mode(int32_t mode);
  * (2 or 4; 0 = automatic).  Applies to later single-box calls from the
  * CALLING THREAD only (each thread starts with all zeros).
  * Results do not depend on the launch shape except for the rounding of the
- * moments (the merge order follows the grid).
+ * moments (the merge order follows the grid, or under a dynamic partition
+ * the chunks).
  */
 CUBE_API int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copies, int32_t unroll);
 
@@ -219,6 +222,52 @@ CUBE_API int cube_set_launch(int32_t threads, int32_t blocks, int32_t hist_copie
 #define CUBE_HIST_PLAIN 1
 #define CUBE_HIST_HOT 2
 CUBE_API int cube_set_hist_mode(int32_t mode);
+
+/*
+ * How the calling thread's later single-box passes (statistics, histogram,
+ * fused, and the read probe) divide the box among thread blocks.  The
+ * two-stage gather of Section 2 leaves the partition of the data open:
+ *   CUBE_PARTITION_AUTO (0)    the tuned choice for the pass; without one,
+ *                              dynamic for large boxes (chunks of 2^18
+ *                              voxels for histogram passes from 2^27 voxels
+ *                              on, of 2^19 for statistics passes from 2^30
+ *                              on), else static; under an explicit
+ *                              cube_set_launch shape, static;
+ *   CUBE_PARTITION_STATIC (1)  every block takes one contiguous range of the
+ *                              box, fixed at launch;
+ *   k in [CUBE_CHUNK_LOG2_MIN, CUBE_CHUNK_LOG2_MAX]
+ *                              dynamic: the box is cut into chunks of about
+ *                              2^k voxels (at most 65536 chunks) and one
+ *                              resident wave of blocks claims them from a
+ *                              counter, so that faster parts of the chip take
+ *                              more of the box.
+ * A dynamic partition keeps one record per chunk, merged in chunk order in
+ * FP64, so its results depend on k and the block shape but not on which
+ * block took which chunk.  It applies to CUBE_ACCUM_FP64MERGE and to the
+ * plain histogram form; other passes keep the static partition.  Counts are
+ * identical under every partition; the moments differ only in rounding.
+ * Returns the thread's previous setting (0, 1 or k), or CUBE_EINVAL for a
+ * value outside these.
+ */
+#define CUBE_PARTITION_AUTO 0
+#define CUBE_PARTITION_STATIC 1
+#define CUBE_CHUNK_LOG2_MIN 12
+#define CUBE_CHUNK_LOG2_MAX 26
+CUBE_API int cube_set_partition(int32_t chunk_log2);
+
+/*
+ * The launch plan the calling thread's next single-box pass of kind
+ * CUBE_Q_STATS, CUBE_Q_HIST or CUBE_Q_FUSED (nbins bins) over the given
+ * DEVICE box would use, as one JSON object written to `out` (at most `cap`
+ * bytes, NUL-terminated): threads per block, blocks, float4 loads per tile,
+ * LDS histogram copies, histogram form ("none", "lds", "hot", "global"),
+ * partition ("static" or "dynamic"), chunk count (0 when static) and work
+ * units.  Launches nothing.  Errors: CUBE_EINVAL for the box errors of the
+ * other calls, an unknown kind, nbins outside [1, CUBE_MAX_BINS], a NULL
+ * `out` or a `cap` too small for the text; CUBE_EDEVICE for a HIP error.
+ */
+CUBE_API int cube_describe_plan(const float *ptr, const int64_t *dims, int32_t kind,
+                                int32_t nbins, char *out, size_t cap);
 
 /*
  * Exact selection and median (Section 3 names the median as a global,
@@ -308,7 +357,9 @@ CUBE_API int cube_read_probe(const float *ptr, const int64_t *dims, int32_t nbin
 
 /*
  * Autotuner.  Times candidate launch shapes (threads, float4 loads per tile,
- * LDS histogram copies, blocks per CU) of one pass kind -- CUBE_Q_STATS,
+ * LDS histogram copies, blocks per CU, the hot-bin histogram form, and the
+ * static or a dynamic partition with chunks of 2^18, 2^19 or 2^20 voxels
+ * under CUBE_ACCUM_FP64MERGE) of one pass kind -- CUBE_Q_STATS,
  * CUBE_Q_HIST or CUBE_Q_FUSED over [lo, hi] -- on the given DEVICE box
  * (`reps` timed launches each) and keeps the fastest for that pass kind,
  * histogram-size class (bins rounded up to a power of two) and box-size

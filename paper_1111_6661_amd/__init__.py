@@ -29,6 +29,8 @@ CUBE_MAX_BINS = 65536
 CUBE_NO_VALID, CUBE_HIST_BAD_RANGE = 1, 2
 CUBE_ACCUM_FP64MERGE, CUBE_ACCUM_KAHAN32, CUBE_ACCUM_NAIVE32 = 0, 1, 2
 CUBE_HIST_AUTO, CUBE_HIST_PLAIN, CUBE_HIST_HOT = 0, 1, 2
+CUBE_PARTITION_AUTO, CUBE_PARTITION_STATIC = 0, 1
+CUBE_CHUNK_LOG2_MIN, CUBE_CHUNK_LOG2_MAX = 12, 26
 
 
 class CubeError(RuntimeError):
@@ -105,6 +107,8 @@ def load() -> C.CDLL:
     lib.cube_set_accum_mode.argtypes = [i32]
     lib.cube_set_launch.argtypes = [i32, i32, i32, i32]
     lib.cube_set_hist_mode.argtypes = [i32]
+    lib.cube_set_partition.argtypes = [i32]
+    lib.cube_describe_plan.argtypes = [P, I64P, i32, i32, C.c_char_p, C.c_size_t]
     lib.cube_shutdown.restype = None
     lib.cube_release_stream.argtypes = [P]
     lib.cube_release_stream.restype = None
@@ -160,7 +164,8 @@ def load() -> C.CDLL:
     for name in ("cube_stats", "cube_hist", "cube_stats_hist", "cube_stats_hist_minmax",
                  "cube_stats_async", "cube_hist_async", "cube_stats_hist_async",
                  "cube_stats_hist_minmax_async", "cube_stats_hist_noalloc",
-                 "cube_set_accum_mode", "cube_set_launch", "cube_set_hist_mode"):
+                 "cube_set_accum_mode", "cube_set_launch", "cube_set_hist_mode",
+                 "cube_set_partition", "cube_describe_plan"):
         getattr(lib, name).restype = C.c_int
     if lib.cube_abi_version() != 1:
         raise RuntimeError("libcubestats ABI version mismatch")
@@ -256,6 +261,21 @@ def cube_set_accum_mode(mode: int) -> int:
 def cube_set_hist_mode(mode: int) -> int:
     """Histogram form of this thread's later single-box passes; returns the previous one."""
     return _check(load().cube_set_hist_mode(mode))
+
+
+def cube_set_partition(chunk_log2: int) -> int:
+    """Partition of this thread's later single-box passes: CUBE_PARTITION_AUTO,
+    CUBE_PARTITION_STATIC, or k for a dynamic partition into chunks of 2^k
+    voxels; returns the previous setting."""
+    return _check(load().cube_set_partition(chunk_log2))
+
+
+def cube_describe_plan(ptr: int, dims, kind: int, nbins: int = 1) -> dict:
+    """The plan of this thread's next single-box pass of `kind` over the box."""
+    import json
+    buf = C.create_string_buffer(512)
+    _check(load().cube_describe_plan(C.c_void_p(ptr), _dims(dims), kind, nbins, buf, 512))
+    return json.loads(buf.value.decode())
 
 
 def cube_set_launch(threads: int = 0, blocks: int = 0, hist_copies: int = 0,

@@ -72,6 +72,9 @@ thread_local int g_hot = -1;
 
 void set_hot_override(int hot) { g_hot = hot; }
 int hot_override() { return g_hot; }
+thread_local int g_chunk = -1;  // partition override: -1 none, 0 static, k chunks of 2^k
+void set_chunk_override(int chunk_log2) { g_chunk = chunk_log2; }
+int chunk_override() { return g_chunk; }
 
 void get_launch(int *threads, int *blocks, int *copies, int *unroll)
 {
@@ -177,6 +180,22 @@ int mark_ws(Workspace *w, hipStream_t s)
 {
     const hipError_t e = hipEventRecord(w->used, s);
     return e == hipSuccess ? CUBE_OK : hip_fail(e, "workspace event");
+}
+
+int stream_counter(hipStream_t s, unsigned int **ctr)
+{
+    Workspace *w = nullptr;
+    const int rc = get_ws(s, &w);
+    if (rc) return rc;
+    *ctr = w->ticket + CHUNK_CTR_WORD;
+    return CUBE_OK;
+}
+
+int stream_used(hipStream_t s)
+{
+    Workspace *w = nullptr;
+    const int rc = get_ws(s, &w);
+    return rc ? rc : mark_ws(w, s);
 }
 
 // Free the workspaces of stream `s` (one per device it was used on; a live
@@ -363,6 +382,18 @@ void collapse(const Box &b, Geom *g)
     g->n_total = b.n;
 }
 
+// The partition of a fully automatic launch (no explicit shape, no tuned
+// entry): dynamic for large boxes, where blocks on the slower XCDs would
+// otherwise set the end of the pass.  Measured with the default shapes on
+// dense boxes of 2^25 to 2^31 voxels: chunks of 2^18 voxels beat the static
+// partition from 2^27 voxels on for histogram passes (by 1-10 %, growing
+// with the box), and chunks of 2^19 from 2^30 on for the statistics pass.
+static int default_chunk_log2(bool hist, uint64_t n)
+{
+    if (hist) return n >= ((uint64_t)1 << 27) ? 18 : 0;
+    return n >= ((uint64_t)1 << 30) ? 19 : 0;
+}
+
 int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
 {
     collapse(b, &p->g);
@@ -371,16 +402,20 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
     // With no explicit shape, use the autotuner's choice for this class.
     TunedShape ts;
     const int kind = stats ? (hist_kind_req ? CUBE_Q_FUSED : CUBE_Q_STATS) : CUBE_Q_HIST;
-    int hot = 0;
-    if (threads == 0 && unroll == 0 && copies_req == 0 && blocks == 0 &&
-        tuned_shape(kind, hist_kind_req ? nbins : 1, b.n, &ts)) {
+    int hot = 0, chunk_log2 = 0, resident = 0;
+    const bool automatic = threads == 0 && unroll == 0 && copies_req == 0 && blocks == 0;
+    if (automatic) chunk_log2 = default_chunk_log2(hist_kind_req != 0, b.n);
+    if (automatic && tuned_shape(kind, hist_kind_req ? nbins : 1, b.n, &ts)) {
         threads = ts.threads;
         unroll = ts.unroll;
         copies_req = ts.copies;
         blocks = (long long)cu_count() * ts.blocks_per_cu;
         hot = ts.hot;
+        chunk_log2 = ts.chunk_log2;
+        resident = ts.blocks_per_cu;
     }
     if (g_hot >= 0) hot = g_hot;
+    if (g_chunk >= 0) chunk_log2 = g_chunk;
     // Histogram passes over boxes under 2^25 voxels default to 256 threads:
     // their launches are short enough that per-block costs dominate (below).
     const bool small = b.n < ((uint64_t)1 << 25);
@@ -409,6 +444,25 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
         }
     }
     p->lds = pass_lds_bytes(stats, p->hist, nbins, p->copies_log2, threads);
+    p->chunks = 0;
+    if (chunk_log2 > 0 && p->hist != HIST_HOT && accum_mode() == CUBE_ACCUM_FP64MERGE) {
+        // Dynamic partition: one persistent wave of blocks (the tuned blocks
+        // per CU, else all that fit; an explicit grid as given) claiming
+        // chunks of about 2^chunk_log2 voxels.
+        const int fit = pass_blocks_per_cu(stats, p->hist, threads, p->lds, p->unroll, true);
+        const long long chunks = chunks_of(b.n, chunk_log2);
+        if (g_blocks == 0) {
+            const int per_cu = resident > 0 && resident < fit ? resident : fit;
+            blocks = (long long)cu_count() * per_cu;
+        }
+        if (blocks > chunks) blocks = chunks;
+        if (blocks > MAX_BLOCKS) blocks = MAX_BLOCKS;
+        if (blocks < 1) blocks = 1;
+        p->chunks = (int)chunks;
+        p->blocks = (int)blocks;
+        cut_rows(p->g, chunks);
+        return CUBE_OK;
+    }
     const int bpc = pass_blocks_per_cu(stats, p->hist, threads, p->lds, p->unroll);
     // At least four blocks per CU over the launch: with one resident
     // histogram block per CU, four waves of blocks measured faster than one
@@ -445,6 +499,13 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
     p->blocks = (int)blocks;
     cut_rows(p->g, blocks);
     return CUBE_OK;
+}
+
+long long chunks_of(uint64_t n, int chunk_log2)
+{
+    const uint64_t c = (n + ((uint64_t)1 << chunk_log2) - 1) >> chunk_log2;
+    if (c < 1) return 1;
+    return c > (uint64_t)REC_CAP ? (long long)REC_CAP : (long long)c;
 }
 
 void cut_rows(Geom &g, long long blocks)
@@ -496,6 +557,7 @@ PassArgs base_args(const Workspace *w, const Plan &p, int nbins)
     a.ticket = w->ticket;
     a.hist_acc = w->hist_acc;
     a.accum_mode = g_accum;
+    a.n_chunks = p.chunks;
     return a;
 }
 
@@ -739,6 +801,51 @@ int cube_set_hist_mode(int32_t mode)
         return fail(CUBE_EINVAL, "unknown histogram form %d", mode);
     const int prev = g_hot < 0 ? CUBE_HIST_AUTO : (g_hot ? CUBE_HIST_HOT : CUBE_HIST_PLAIN);
     g_hot = mode == CUBE_HIST_AUTO ? -1 : (mode == CUBE_HIST_HOT ? 1 : 0);
+    return prev;
+}
+
+int cube_describe_plan(const float *ptr, const int64_t *dims, int32_t kind, int32_t nbins,
+                       char *out, size_t cap)
+{
+    CUBE_GUARD_BEGIN
+    g_err.clear();
+    if (kind != CUBE_Q_STATS && kind != CUBE_Q_HIST && kind != CUBE_Q_FUSED)
+        return fail(CUBE_EINVAL, "plan kinds: CUBE_Q_STATS, CUBE_Q_HIST, CUBE_Q_FUSED");
+    if (nbins < 1 || nbins > CUBE_MAX_BINS)
+        return fail(CUBE_EINVAL, "nbins=%d outside [1, %d]", nbins, CUBE_MAX_BINS);
+    if (!out || cap == 0) return fail(CUBE_EINVAL, "out is NULL or cap is 0");
+    Box b;
+    int rc = check_box(ptr, dims, &b);
+    if (rc) return rc;
+    if ((rc = check_box_device(&b))) return rc;
+    if (b.n == 0) return fail(CUBE_EINVAL, "an empty box launches nothing");
+    Plan p;
+    if ((rc = make_plan(b, kind != CUBE_Q_HIST, kind == CUBE_Q_STATS ? 0 : 1, nbins, &p)))
+        return rc;
+    static const char *forms[] = {"none", "lds", "global", "hot"};
+    const int n = snprintf(out, cap,
+                           "{\"threads\": %d, \"blocks\": %d, \"unroll\": %d, \"copies\": %d, "
+                           "\"hist\": \"%s\", \"partition\": \"%s\", \"chunks\": %d, "
+                           "\"units\": %lld}",
+                           p.threads, p.blocks, p.unroll,
+                           p.hist == HIST_NONE || p.hist == HIST_GLOBAL ? 0 : 1 << p.copies_log2,
+                           forms[p.hist], p.chunks > 0 ? "dynamic" : "static", p.chunks,
+                           (long long)p.g.n_units);
+    if (n < 0 || (size_t)n >= cap) return fail(CUBE_EINVAL, "cap %zu too small for the plan", cap);
+    return CUBE_OK;
+    CUBE_GUARD_END
+}
+
+int cube_set_partition(int32_t chunk_log2)
+{
+    if (chunk_log2 != CUBE_PARTITION_AUTO && chunk_log2 != CUBE_PARTITION_STATIC &&
+        (chunk_log2 < CUBE_CHUNK_LOG2_MIN || chunk_log2 > CUBE_CHUNK_LOG2_MAX))
+        return fail(CUBE_EINVAL, "partition %d: 0 (automatic), 1 (static) or chunks of 2^k "
+                    "voxels, k in [%d, %d]", chunk_log2, CUBE_CHUNK_LOG2_MIN, CUBE_CHUNK_LOG2_MAX);
+    const int prev = g_chunk < 0 ? CUBE_PARTITION_AUTO
+                                 : (g_chunk == 0 ? CUBE_PARTITION_STATIC : g_chunk);
+    g_chunk = chunk_log2 == CUBE_PARTITION_AUTO ? -1
+              : (chunk_log2 == CUBE_PARTITION_STATIC ? 0 : chunk_log2);
     return prev;
 }
 

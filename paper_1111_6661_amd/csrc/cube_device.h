@@ -283,38 +283,56 @@ __device__ __forceinline__ Summary<T> shfl_xor_summary(const Summary<T> &s, int 
     return o;
 }
 
-// The global stage: every thread folds a fixed slice of the wavefront
-// records in order, then a fixed xor-tree inside each wavefront, then the
-// wavefront summaries in order.  Deterministic for a given grid.
+// The (count, mean, m2) of one wavefront record: its pivoted sums
+// S1 = sum(x - K), S2 = sum((x - K)^2) give mean = K + S1/n and
+// m2 = S2 - S1^2/n (clamped at 0).
 template <typename T, int ACC>
-__device__ Summary<T> merge_records(const WaveRec *recs, int n_recs)
+__device__ __forceinline__ void moments_of(const WaveRec &w, T &mb, T &m2b)
+{
+    const double nb = (double)w.n_valid;
+    if (ACC == CUBE_ACCUM_NAIVE32) {
+        const T S1 = (T)w.s1h, S2 = (T)w.s2h, n = (T)nb;
+        mb = S1 / n;
+        m2b = S2 - S1 * S1 / n;
+    } else {
+        const T S1 = (T)w.s1h + (T)w.s1l;
+        const T S2 = (T)w.s2h + (T)w.s2l;
+        mb = (T)w.K + S1 / (T)nb;
+        m2b = S2 - S1 * S1 / (T)nb;
+    }
+    if (m2b < (T)0) m2b = (T)0;
+}
+
+// A chunk record already holds its mean and m2.
+template <typename T, int ACC>
+__device__ __forceinline__ void moments_of(const ChunkRec &c, T &mb, T &m2b)
+{
+    mb = (T)c.mean;
+    m2b = (T)c.m2;
+}
+
+// The global stage: every thread folds a fixed slice of the records (wave
+// records, or chunk records in chunk order) in order, then a fixed xor-tree
+// inside each wavefront, then the wavefront summaries in order.
+// Deterministic for a given record count.
+template <typename T, int ACC, typename R = WaveRec>
+__device__ Summary<T> merge_records(const R *recs, int n_recs)
 {
     const int tid = threadIdx.x, B = blockDim.x;
     const int r0 = (int)(((long long)n_recs * tid) / B);
     const int r1 = (int)(((long long)n_recs * (tid + 1)) / B);
     Summary<T> s = {0.0, (T)0, (T)0, INFINITY, -INFINITY, 0ull, 0ull, 0ull};
     for (int r = r0; r < r1; ++r) {
-        const WaveRec w = recs[r];
+        const R w = recs[r];
         s.below += w.below;
         s.above += w.above;
         if (w.n_valid == 0) continue;
         s.nv += w.n_valid;
         s.mn = fminf(s.mn, w.mn);
         s.mx = fmaxf(s.mx, w.mx);
-        const double nb = (double)w.n_valid;
         T mb, m2b;
-        if (ACC == CUBE_ACCUM_NAIVE32) {
-            const T S1 = (T)w.s1h, S2 = (T)w.s2h, n = (T)nb;
-            mb = S1 / n;
-            m2b = S2 - S1 * S1 / n;
-        } else {
-            const T S1 = (T)w.s1h + (T)w.s1l;
-            const T S2 = (T)w.s2h + (T)w.s2l;
-            mb = (T)w.K + S1 / (T)nb;
-            m2b = S2 - S1 * S1 / (T)nb;
-        }
-        if (m2b < (T)0) m2b = (T)0;
-        chan_merge<T>(s.n, s.mean, s.m2, nb, mb, m2b);
+        moments_of<T, ACC>(w, mb, m2b);
+        chan_merge<T>(s.n, s.mean, s.m2, (double)w.n_valid, mb, m2b);
     }
     for (int off = 1; off < 64; off <<= 1) {
         Summary<T> o = shfl_xor_summary(s, off);
@@ -555,6 +573,58 @@ __device__ __forceinline__ void write_wave_record(const Lane &L, const Wave &W, 
     }
 }
 
+// The record of one chunk of a dynamic partition, formed by the first
+// wavefront from the block's wavefront records of that chunk (`parts`, in
+// LDS, `nw` of them): lane i takes record i, the lanes are merged in FP64 by
+// a fixed xor-tree (the lower lane of each pair on the left), and lane 0
+// writes the result.  Without STATS only the counts are kept.
+template <bool STATS>
+__device__ __forceinline__ void write_chunk_record(const WaveRec *parts, int nw, ChunkRec *dst)
+{
+    const int lane = threadIdx.x & 63;
+    Summary<double> s = {0.0, 0.0, 0.0, INFINITY, -INFINITY, 0ull, 0ull, 0ull};
+    if (lane < nw) {
+        const WaveRec w = parts[lane];
+        s.below = w.below;
+        s.above = w.above;
+        s.nv = w.n_valid;
+        if (STATS && w.n_valid) {
+            s.n = (double)w.n_valid;
+            s.mn = w.mn;
+            s.mx = w.mx;
+            moments_of<double, CUBE_ACCUM_FP64MERGE>(w, s.mean, s.m2);
+        }
+    }
+    for (int off = 1; off < MAX_WAVES; off <<= 1) {
+        if (STATS) {
+            Summary<double> o = shfl_xor_summary(s, off);
+            if ((lane & off) == 0) {
+                summary_merge(s, o);
+            } else {
+                summary_merge(o, s);
+                s = o;
+            }
+        } else {
+            s.nv += __shfl_xor(s.nv, off);
+            s.below += __shfl_xor(s.below, off);
+            s.above += __shfl_xor(s.above, off);
+        }
+    }
+    if (lane == 0) {
+        ChunkRec c;
+        c.mean = s.mean;
+        c.m2 = s.m2;
+        c.mn = s.mn;
+        c.mx = s.mx;
+        c.pad0 = c.pad1 = 0u;
+        c.n_valid = s.nv;
+        c.below = s.below;
+        c.above = s.above;
+        c.pad2 = 0ull;
+        *dst = c;
+    }
+}
+
 // Add the block's LDS sub-histograms into the global accumulators (one
 // atomic per non-empty bin).  Starts with a barrier.
 __device__ __forceinline__ void hist_flush(const unsigned int *lds, int nbins, int copies_log2,
@@ -676,8 +746,8 @@ __device__ __forceinline__ void extended_real_moments(cube_stats_t &o)
 // the block call it), then thread 0 writes the result and, when `range_out`
 // is given, the [min, max] histogram range with its FP32 scale.  Returns the
 // total valid / below / above counts to every thread.
-template <int ACC>
-__device__ void finish_stats(const WaveRec *recs, int n_recs, int accum_mode,
+template <int ACC, typename R = WaveRec>
+__device__ void finish_stats(const R *recs, int n_recs, int accum_mode,
                              unsigned long long n_total, cube_stats_t *out,
                              HistRange *range_out, int nbins, unsigned long long &nv,
                              unsigned long long &below, unsigned long long &above)
@@ -685,11 +755,11 @@ __device__ void finish_stats(const WaveRec *recs, int n_recs, int accum_mode,
     float fmn, fmx;
     double mean, m2;
     if (accum_mode == CUBE_ACCUM_FP64MERGE) {
-        const Summary<double> S = merge_records<double, ACC>(recs, n_recs);
+        const Summary<double> S = merge_records<double, ACC, R>(recs, n_recs);
         nv = S.nv; below = S.below; above = S.above;
         fmn = S.mn; fmx = S.mx; mean = S.mean; m2 = S.m2;
     } else {
-        const Summary<float> S = merge_records<float, ACC>(recs, n_recs);
+        const Summary<float> S = merge_records<float, ACC, R>(recs, n_recs);
         nv = S.nv; below = S.below; above = S.above;
         fmn = S.mn; fmx = S.mx; mean = (double)S.mean; m2 = (double)S.m2;
     }

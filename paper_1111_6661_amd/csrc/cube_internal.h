@@ -22,6 +22,21 @@ struct alignas(16) WaveRec {
 };
 static_assert(sizeof(WaveRec) == 64, "WaveRec is 64 bytes");
 
+// One partial result per chunk of a pass with a dynamic partition: the
+// chunk's wavefront records merged in FP64 (count, mean, sum of squared
+// deviations about the mean, extrema, below / above counts).
+struct alignas(16) ChunkRec {
+    double mean, m2;
+    float mn, mx;
+    unsigned int pad0, pad1;
+    unsigned long long n_valid, below, above, pad2;
+};
+static_assert(sizeof(ChunkRec) == 64, "ChunkRec is 64 bytes");
+
+// The chunk counter of a pass with a dynamic partition is this word of the
+// ticket buffer (a separate 128-byte line from the ticket itself).
+constexpr int CHUNK_CTR_WORD = 32;
+
 // A histogram range as the kernels use it.  ok: 1 valid, 0 invalid range,
 // 2 no valid voxel (the two-pass range of an all-blank box).
 struct HistRange {
@@ -54,8 +69,10 @@ struct PassArgs {
     int32_t copies_log2;         // LDS sub-histogram copies = 1 << copies_log2
     HistRange range;             // the given range (when dev_range is null)
     const HistRange *dev_range;  // range formed on the device by a stats pass
-    WaveRec *recs;               // gridDim.x * waves-per-block records
-    unsigned int *ticket;        // last-block-done counter, 0 between launches
+    WaveRec *recs;               // gridDim.x * waves-per-block records (static
+                                 // partition), or n_chunks ChunkRecs (dynamic)
+    unsigned int *ticket;        // last-block-done counter and, at word
+                                 // CHUNK_CTR_WORD, the chunk counter; 0 between launches
     unsigned long long *hist_acc;// nbins global accumulators, 0 between launches
     cube_stats_t *out;           // device result (stats passes)
     unsigned long long *counts;  // device counts, nbins + 3 (histogram passes)
@@ -63,6 +80,7 @@ struct PassArgs {
     int32_t accum_mode;          // CUBE_ACCUM_*
     int32_t want_range;          // pass 1 of a two-pass call: write out_range
     int32_t accumulate;          // add the counts to `counts` instead of writing them
+    int32_t n_chunks;            // 0: static partition; else chunks claimed at run time
 };
 
 // Kernel launchers (cube_kernels.hip).  `stats`: compute the statistics;
@@ -76,7 +94,9 @@ hipError_t launch_pass(const PassArgs &a, bool stats, int hist, int threads,
 size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int threads);
 
 // Occupancy of one pass configuration: resident blocks per CU.
-int pass_blocks_per_cu(bool stats, int hist, int threads, size_t lds_bytes, int unroll);
+// `dynamic`: of the dynamic-partition kernel.
+int pass_blocks_per_cu(bool stats, int hist, int threads, size_t lds_bytes, int unroll,
+                       bool dynamic = false);
 
 // ------------------------------------------------ host helpers (cube_capi.hip)
 // A validated box: extents, pitches (defaults resolved) and voxel count.
@@ -89,6 +109,7 @@ struct Box {
 struct Plan {
     Geom g;
     int threads, blocks, copies_log2, hist, unroll;
+    int chunks;  // 0: static partition; else the dynamic partition's chunk count
     size_t lds;
 };
 
@@ -151,6 +172,12 @@ void cut_rows(Geom &g, long long blocks);
 int run_pass(const Box &b, bool stats, bool hist, int nbins, const HistRange &range,
              const HistRange *dev_range, cube_stats_t *dev_out, unsigned long long *dev_counts,
              bool accumulate, hipStream_t s);
+// Two counter words (0 between launches; a kernel that uses them returns
+// them to 0) in the calling device's workspace of stream `s`, at the chunk
+// counter of the single-box pass; after queueing the kernel, stream_used(s)
+// records the use so that the workspace outlives it.
+int stream_counter(hipStream_t s, unsigned int **ctr);
+int stream_used(hipStream_t s);
 // Free the calling device's workspace of stream `s` (waits for its last
 // use); a library-owned stream releases it before hipStreamDestroy.
 void release_ws(hipStream_t s);
@@ -167,7 +194,8 @@ void quant_release();
 // A launch shape chosen by the autotuner (cube_tune.hip).
 struct TunedShape {
     int threads, unroll, copies, blocks_per_cu;
-    int hot;  // 1: the hot-bin histogram (HIST_HOT) instead of HIST_LDS
+    int hot;         // 1: the hot-bin histogram (HIST_HOT) instead of HIST_LDS
+    int chunk_log2;  // 0: static partition; k: dynamic, chunks of 2^k voxels
     float ms;
 };
 // The calling thread's hot-bin override for later single-box histogram
@@ -175,6 +203,14 @@ struct TunedShape {
 // autotuner sets it per candidate.
 void set_hot_override(int hot);
 int hot_override();
+// The calling thread's partition override for later single-box passes: -1
+// none (tuned or default), 0 static, k >= 1 dynamic with chunks of 2^k
+// voxels (cube_set_partition).
+void set_chunk_override(int chunk_log2);
+int chunk_override();
+// The chunk count of a dynamic partition of n voxels into chunks of
+// 2^chunk_log2 voxels (at least 1, at most the record capacity).
+long long chunks_of(uint64_t n, int chunk_log2);
 // The tuned shape for (pass kind CUBE_Q_*, nbins, voxels), if any.
 bool tuned_shape(int kind, int nbins, uint64_t voxels, TunedShape *out);
 

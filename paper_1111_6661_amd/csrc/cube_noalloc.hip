@@ -94,7 +94,15 @@ extern "C" int cube_stats_hist_noalloc(const float *ptr, const int64_t *dims, fl
     Plan p;
     if ((rc = make_plan(b, true, 1, nbins, &p))) return rc;
     const long long waves = p.threads / 64;
-    if ((long long)p.blocks * waves > (long long)NA_RECS) {
+    if (p.chunks > 0) {
+        // A dynamic partition keeps one record per chunk: at most NA_RECS
+        // chunks (each block still flushes its LDS counters in time).
+        if (p.chunks > (int)NA_RECS) {
+            p.chunks = (int)NA_RECS;
+            if (p.blocks > p.chunks) p.blocks = p.chunks;
+            cut_rows(p.g, p.chunks);
+        }
+    } else if ((long long)p.blocks * waves > (long long)NA_RECS) {
         int t = 0, bl = 0, c = 0, u = 0;
         get_launch(&t, &bl, &c, &u);
         if (bl != 0)
@@ -131,6 +139,7 @@ extern "C" int cube_stats_hist_noalloc(const float *ptr, const int64_t *dims, fl
     a.out = dev_out;
     a.counts = (unsigned long long *)dev_counts;
     a.accum_mode = accum_mode();
+    a.n_chunks = p.chunks;
     e = launch_pass(a, true, p.hist, p.threads, p.blocks, p.lds, p.unroll, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return CUBE_OK;

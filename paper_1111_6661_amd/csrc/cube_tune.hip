@@ -1,8 +1,9 @@
 // cube_tune.hip -- the autotuner of the single-box pass.
 //
 // It times candidate launch shapes (threads per block, float4 loads per
-// pipelined tile, LDS histogram copies, blocks per CU, and for histograms the
-// plain or the hot-bin LDS form) of one pass kind on
+// pipelined tile, LDS histogram copies, blocks per CU, the static or a
+// dynamic partition with its chunk size, and for histograms the plain or the
+// hot-bin LDS form) of one pass kind on
 // the caller's own data with HIP events, and keeps the fastest shape per
 // (pass kind, histogram-size class, box-size class) in a table that the
 // launch planner consults when no explicit shape is set.  The table can be
@@ -121,6 +122,10 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
         return hip_fail(e, "tune buffers");
     }
     const int cus = cu_count();
+    // Partitions: static, and dynamic with chunks of 2^18, 2^19, 2^20 voxels
+    // (the dynamic pass exists for FP64MERGE moments only).
+    const int part_c[] = {0, 18, 19, 20};
+    const bool dyn_ok = accum_mode() == CUBE_ACCUM_FP64MERGE;
     const int hot_c[] = {0, 1};
     const int threads_c[] = {256, 512, 1024};
     const int unroll_c[] = {2, 4};
@@ -144,18 +149,25 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
         }
     };
     const int prev_hot = hot_override();
+    const int prev_chunk = chunk_override();
     rc = CUBE_OK;
+    for (int part : part_c)
     for (int hot : hot_c)
     for (int t : threads_c)
         for (int u : unroll_c)
             for (int c : copies_c) {
+                if (rc) break;
+                if (part && (hot || !dyn_ok)) continue;
                 if (kind == CUBE_Q_STATS && (c != copies_c[0] || hot)) continue;
                 // The LDS histogram must fit one block (160 KiB); the hot-bin
                 // form exists for LDS histograms only.
                 if (kind != CUBE_Q_STATS && ((size_t)(nbins + 2) * c * 4 > 160 * 1024)) continue;
                 if (hot && nbins > 32768) continue;
                 set_hot_override(hot);
+                set_chunk_override(part);
                 for (int bpc : bpc_c) {
+                    // A dynamic partition runs one resident wave of blocks.
+                    if (part && bpc > 2) continue;
                     const int blocks = std::min(cus * bpc, 4096);
                     if ((rc = cube_set_launch(t, blocks, kind == CUBE_Q_STATS ? 0 : c, u))) break;
                     if ((rc = run_one())) break;  // warm-up
@@ -175,14 +187,15 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
                     cd.sh.copies = kind == CUBE_Q_STATS ? 0 : c;
                     cd.sh.blocks_per_cu = bpc;
                     cd.sh.hot = hot;
+                    cd.sh.chunk_log2 = part;
                     cd.sh.ms = ms / reps;
                     cd.ms = ms / reps;
                     cands.push_back(cd);
                 }
-                if (rc) break;
             }
     cube_set_launch(prev_t, prev_b, prev_c, prev_u);
     set_hot_override(prev_hot);
+    set_chunk_override(prev_chunk);
     hipStreamSynchronize(s);
     release_ws(s);  // before the stream goes: its workspace is keyed by it
     hipFree(d_out);
@@ -203,8 +216,9 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
         auto fmt = [&](const TunedShape &sh) {
             snprintf(buf, sizeof buf,
                      "{\"threads\": %d, \"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, "
-                     "\"hot\": %d, \"ms\": %.5f}",
-                     sh.threads, sh.unroll, sh.copies, sh.blocks_per_cu, sh.hot, sh.ms);
+                     "\"hot\": %d, \"chunk_log2\": %d, \"ms\": %.5f}",
+                     sh.threads, sh.unroll, sh.copies, sh.blocks_per_cu, sh.hot, sh.chunk_log2,
+                     sh.ms);
             return std::string(buf);
         };
         rep += fmt(cands[0].sh) + ", \"worst\": " + fmt(cands.back().sh);
@@ -239,10 +253,10 @@ int cube_tune_save(const char *path)
         fprintf(f,
                 "%s\n  {\"kind\": %d, \"bins_log2\": %d, \"size_log2\": %d, \"threads\": %d, "
                 "\"unroll\": %d, \"copies\": %d, \"blocks_per_cu\": %d, \"ms\": %.5f, "
-                "\"hot\": %d}",
+                "\"hot\": %d, \"chunk_log2\": %d}",
                 first ? "" : ",", kv.first.kind, kv.first.bins_log2, kv.first.size_log2,
                 kv.second.threads, kv.second.unroll, kv.second.copies, kv.second.blocks_per_cu,
-                kv.second.ms, kv.second.hot);
+                kv.second.ms, kv.second.hot, kv.second.chunk_log2);
         first = false;
     }
     fprintf(f, "\n]}\n");
@@ -286,18 +300,22 @@ int cube_tune_load(const char *path)
             ++n;
             continue;
         }
-        int kind, bl, sl, th, un, co, bp, hot = 0;
+        int kind, bl, sl, th, un, co, bp, hot = 0, cl = 0;
         double ms;
-        // "hot" is optional (tables written before the hot-bin form have none).
+        // "hot" and "chunk_log2" are optional (tables written before the
+        // hot-bin form or the dynamic partition have none).
         const int got = sscanf(strchr(line, '{') ? strchr(line, '{') : line,
                                "{\"kind\": %d, \"bins_log2\": %d, \"size_log2\": %d, "
                                "\"threads\": %d, \"unroll\": %d, \"copies\": %d, "
-                               "\"blocks_per_cu\": %d, \"ms\": %lf, \"hot\": %d}",
-                               &kind, &bl, &sl, &th, &un, &co, &bp, &ms, &hot);
-        if (got == 8 || got == 9) {
+                               "\"blocks_per_cu\": %d, \"ms\": %lf, \"hot\": %d, "
+                               "\"chunk_log2\": %d}",
+                               &kind, &bl, &sl, &th, &un, &co, &bp, &ms, &hot, &cl);
+        if (got >= 8) {
             if ((th != 256 && th != 512 && th != 1024) || (un != 2 && un != 4) ||
                 co < 0 || co > 32 || (co & (co - 1)) || bp < 1 || bp > 64 ||
-                (hot != 0 && hot != 1)) {
+                (hot != 0 && hot != 1) ||
+                (cl != 0 && (cl < CUBE_CHUNK_LOG2_MIN || cl > CUBE_CHUNK_LOG2_MAX)) ||
+                (cl != 0 && hot != 0)) {
                 fclose(f);
                 return fail(CUBE_EINVAL, "%s: bad entry", path);
             }
@@ -307,6 +325,7 @@ int cube_tune_load(const char *path)
             sh.copies = co;
             sh.blocks_per_cu = bp;
             sh.hot = hot;
+            sh.chunk_log2 = cl;
             sh.ms = (float)ms;
             t[TuneKey{kind, bl, sl}] = sh;
             ++n;

@@ -110,6 +110,23 @@ def test_mode_and_launch_setters_validate():
     assert cs.cube_set_hist_mode(cs.CUBE_HIST_HOT) == cs.CUBE_HIST_AUTO
     assert cs.cube_set_hist_mode(cs.CUBE_HIST_PLAIN) == cs.CUBE_HIST_HOT
     assert cs.cube_set_hist_mode(cs.CUBE_HIST_AUTO) == cs.CUBE_HIST_PLAIN
+    for bad in (-1, 2, cs.CUBE_CHUNK_LOG2_MIN - 1, cs.CUBE_CHUNK_LOG2_MAX + 1):
+        assert _code(cs.cube_set_partition, bad)[0] == cs.CUBE_EINVAL
+    assert cs.cube_set_partition(18) == cs.CUBE_PARTITION_AUTO
+    assert cs.cube_set_partition(cs.CUBE_PARTITION_STATIC) == 18
+    assert cs.cube_set_partition(cs.CUBE_PARTITION_AUTO) == cs.CUBE_PARTITION_STATIC
+
+
+def test_describe_plan_rejects_bad_arguments_before_gpu():
+    buf = C.create_string_buffer(256)
+    d = (C.c_int64 * 5)(8, 1, 1, 0, 0)
+    lib = cs.load()
+    assert lib.cube_describe_plan(C.c_void_p(0x1000), d, 7, 16, buf, 256) == cs.CUBE_EINVAL
+    assert lib.cube_describe_plan(C.c_void_p(0x1000), d, cs.CUBE_Q_FUSED, 0, buf, 256) == \
+        cs.CUBE_EINVAL
+    assert lib.cube_describe_plan(C.c_void_p(0x1000), d, cs.CUBE_Q_FUSED, 16, None, 256) == \
+        cs.CUBE_EINVAL
+    assert "kind" in cs.last_error() or "NULL" in cs.last_error()
 
 
 def test_mode_is_per_thread():
@@ -195,6 +212,20 @@ def test_tuning_table_round_trip(tmp_path):
         bad_hot.write_text(open(hot).read().replace('"hot": 1', '"hot": 2'))
         with pytest.raises(cs.CubeError):
             cs.cube_tune_load(str(bad_hot))
+        # the optional partition field: a chunk size round-trips; sizes outside
+        # the allowed range, and a dynamic partition with the hot-bin form, are refused
+        dyn = tmp_path / "dyn.json"
+        dyn.write_text(open(hot).read().replace('"hot": 1', '"hot": 0, "chunk_log2": 19'))
+        cs.cube_tune_clear()
+        assert cs.cube_tune_load(str(dyn)) == 1
+        cs.cube_tune_save(str(out))
+        assert '"hot": 0, "chunk_log2": 19' in open(out).read()
+        for bad in ('"hot": 0, "chunk_log2": 11', '"hot": 0, "chunk_log2": 27',
+                    '"hot": 1, "chunk_log2": 19'):
+            (tmp_path / "baddyn.json").write_text(
+                open(dyn).read().replace('"hot": 0, "chunk_log2": 19', bad))
+            with pytest.raises(cs.CubeError):
+                cs.cube_tune_load(str(tmp_path / "baddyn.json"))
     finally:
         cs.cube_tune_clear()
 

@@ -53,6 +53,11 @@ def test_brick16g_full_cube(cs):
     r = synth.WORKLOADS[name]
     nb = synth.HIST_BINS[name]
     t = synth.cube_tensor(r, synth.BASE_SEED + 1, device="cuda")
+    # the shipped table's plan for this box: the dynamic partition bench.py times
+    ptr, d = cs.box_of(t)
+    plan = cs.cube_describe_plan(ptr, d, cs.CUBE_Q_FUSED, nb)
+    print("brick16g fused plan:", plan)
+    assert plan["partition"] == "dynamic" and plan["chunks"] == r.n >> 18, plan
     st_fused_ref = cs.stats(t)
     st, counts = cs.stats_hist(t, st_fused_ref.min, st_fused_ref.max, nb)
     st2, counts2 = cs.stats_hist_minmax(t, nb)
