@@ -225,8 +225,9 @@ CUBE_API int cube_set_hist_mode(int32_t mode);
 
 /*
  * How the calling thread's later single-box passes (statistics, histogram,
- * fused, and the read probe) divide the box among thread blocks.  The
- * two-stage gather of Section 2 leaves the partition of the data open:
+ * fused, the read probe, and the full-box passes of selection, median and
+ * quantiles) divide the box among thread blocks.  The two-stage gather of
+ * Section 2 leaves the partition of the data open:
  *   CUBE_PARTITION_AUTO (0)    the tuned choice for the pass; without one,
  *                              dynamic for large boxes (chunks of 2^18
  *                              voxels for histogram passes from 2^27 voxels
@@ -244,8 +245,10 @@ CUBE_API int cube_set_hist_mode(int32_t mode);
  * A dynamic partition keeps one record per chunk, merged in chunk order in
  * FP64, so its results depend on k and the block shape but not on which
  * block took which chunk.  It applies to CUBE_ACCUM_FP64MERGE and to the
- * plain histogram form; other passes keep the static partition.  Counts are
- * identical under every partition; the moments differ only in rounding.
+ * plain histogram form; other passes keep the static partition.  Counts,
+ * selections, medians and quantiles are identical under every partition;
+ * the moments differ only in rounding.  Selection passes follow the same
+ * automatic rule as histogram passes (chunks of 2^18 voxels from 2^27).
  * Returns the thread's previous setting (0, 1 or k), or CUBE_EINVAL for a
  * value outside these.
  */

@@ -58,6 +58,7 @@ struct QuantArgs {
     const unsigned char *tab;      // T1 (4096 bytes), T2, T3, back to back
     unsigned long long *acc;       // slots << width counters, zero on entry
     unsigned long long *n_valid;   // pass 0: valid voxels, zero on entry
+    Claim claim;                   // the partition (its counter zero on entry)
 };
 
 // NL: prefix levels of this pass (0 for the first pass).
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
     st.clog = a.copies_log2;
     st.cbase = tid & 63 & ((1 << a.copies_log2) - 1);
     st.valid = 0u;
-    scan_box(a.g, st);
+    scan_box(a.g, st, a.claim);
     // Every lane of a wavefront holds the same count (sums of ballots).
     if (NL == 0 && (tid & 63) == 0 && st.valid) atomicAdd(&s_valid, st.valid);
     __syncthreads();
@@ -143,7 +144,7 @@ __global__ void __launch_bounds__(Q_THREADS) k_quant(QuantArgs a)
 }
 
 struct QuantWorkspace {
-    unsigned long long *acc = nullptr;    // Q_ACC counters + 1 valid counter
+    unsigned long long *acc = nullptr;    // Q_ACC counters, the valid counter, the chunk counter
     unsigned char *tab = nullptr;         // the prefix tables
     unsigned long long *h_acc = nullptr;  // pinned copy of the counters
     unsigned char *h_tab = nullptr;       // pinned staging of the tables
@@ -161,7 +162,7 @@ int quant_ws(QuantWorkspace **out)
     if (!g_qws_ready[dev]) {
         QuantWorkspace &w = g_qws[dev];
         hipError_t e;
-        if ((e = hipMalloc(&w.acc, (Q_ACC + 1) * 8)) != hipSuccess ||
+        if ((e = hipMalloc(&w.acc, (Q_ACC + 2) * 8)) != hipSuccess ||
             (e = hipMalloc(&w.tab, Q_TAB)) != hipSuccess ||
             (e = hipHostMalloc(&w.h_acc, (Q_ACC + 1) * 8)) != hipSuccess ||
             (e = hipHostMalloc(&w.h_tab, Q_TAB)) != hipSuccess)
@@ -176,7 +177,7 @@ int quant_ws(QuantWorkspace **out)
 // launch, read the counters back (slots << width of them, and the valid
 // count after the first pass).  All on the null stream; returns after the
 // copy.  nl: prefix levels (0 for the first pass); w2, w3 their widths.
-int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, int width,
+int quant_pass(QuantWorkspace *w, const Box &box, const Geom &g, int nl, int shift, int width,
                int w2, int w3, int slots, int t2_bytes, int t3_bytes)
 {
     hipError_t e;
@@ -185,7 +186,7 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, 
     const size_t tab = nl == 0 ? 0 : 4096 + (nl >= 2 ? t2_bytes : 0) + (nl >= 3 ? t3_bytes : 0);
     if (n > (size_t)Q_ACC || slots > Q_MAX_RANKS || tab > Q_TAB || hist * 4 + tab > Q_LDS)
         return fail(CUBE_EINVAL, "quantile pass too large");
-    if ((e = hipMemsetAsync(w->acc, 0, (Q_ACC + 1) * 8, nullptr)) != hipSuccess)
+    if ((e = hipMemsetAsync(w->acc, 0, (Q_ACC + 2) * 8, nullptr)) != hipSuccess)
         return hip_fail(e, "quantile counters");
     if (tab &&
         (e = hipMemcpyAsync(w->tab, w->h_tab, tab, hipMemcpyHostToDevice, nullptr)) != hipSuccess)
@@ -216,6 +217,11 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, 
         (e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
             hipSuccess)
         return hip_fail(e, "quantile LDS");
+    int blocks = 0, chunks = 0;
+    const int rc = scan_plan(box, k, Q_THREADS, lds, &blocks, &chunks);
+    if (rc) return rc;
+    a.claim.ctr = (unsigned int *)(w->acc + Q_ACC + 1);
+    a.claim.nc = chunks;
     void *args[] = {&a};
     if ((e = hipLaunchKernel(k, dim3((unsigned)blocks), dim3(Q_THREADS), args, lds, nullptr)) !=
         hipSuccess)
@@ -232,13 +238,13 @@ int quant_pass(QuantWorkspace *w, const Geom &g, int blocks, int nl, int shift, 
 // The passes on the GPU for the host-side plan (cube_quantile_plan.h).
 struct GpuPasses {
     QuantWorkspace *w;
+    Box box;
     Geom g;
-    int blocks;
     int reads = 0;  // reads of the box so far
     int first(const unsigned long long **counts, unsigned long long *n)
     {
         ++reads;
-        const int rc = quant_pass(w, g, blocks, 0, 20, 12, 0, 0, 1, 0, 0);
+        const int rc = quant_pass(w, box, g, 0, 20, 12, 0, 0, 1, 0, 0);
         if (rc) return rc;
         *counts = w->h_acc;
         *n = w->h_acc[Q_ACC];
@@ -248,7 +254,7 @@ struct GpuPasses {
     int refine(const QuantPassSpec &s, const unsigned char *, const unsigned long long **counts)
     {
         ++reads;
-        const int rc = quant_pass(w, g, blocks, s.nl, s.shift, s.width, s.w2, s.w3, s.slots,
+        const int rc = quant_pass(w, box, g, s.nl, s.shift, s.width, s.w2, s.w3, s.slots,
                                   s.t2_bytes, s.t3_bytes);
         if (rc) return rc;
         *counts = w->h_acc;
@@ -263,8 +269,13 @@ int run_quantiles(const Box &box, const double *q, int m, double *out, uint64_t 
     if (rc) return rc;
     GpuPasses P;
     P.w = w;
-    P.blocks = cu_count() * 2;
-    scan_geom(box, P.blocks, &P.g);
+    P.box = box;
+    // Work units for the static grid (two blocks per CU) and for every chunk
+    // of a dynamic partition (scan_plan's automatic or set chunk size).
+    const int cl = scan_chunk_log2(box);
+    const long long units = cl ? chunks_of(box.n, cl) : 0;
+    const long long grid = (long long)cu_count() * 2;
+    scan_geom(box, units > grid ? units : grid, &P.g);
     rc = quantiles_run(P, q, m, out, n_valid_out, w->h_tab, 1);
     if (rc == 1) return fail(CUBE_EINVAL, "no valid voxel");
     if (rc == CUBE_OK) g_quant_reads = P.reads;

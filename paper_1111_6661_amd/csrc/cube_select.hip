@@ -49,6 +49,7 @@ struct SelectArgs {
     float *cand;                 // per-block candidate regions, cand_cap floats each
     unsigned int *cand_n;        // voxels each block copied (pass 1)
     unsigned int cand_cap;
+    Claim claim;                 // the partition of the full-box passes
 };
 
 // Pass p histograms key bits [shift, shift + width): widths 12, 12, 8.
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
         CountStep<true> cc;
         cc.c = c;
         cc.valid = 0;
-        scan_box(a.g, cc);
+        scan_box(a.g, cc, a.claim);
         __syncthreads();
         if (tid == 0) {
             a.cand_n[blockIdx.x] = min(s_cnt, a.cand_cap);
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
             select_step<1>(xv, cs.valid, c);
         }
     } else {
-        scan_box(a.g, cs);
+        scan_box(a.g, cs, a.claim);
     }
     const unsigned long long valid = cs.valid;
     const int lane = tid & 63;
@@ -250,7 +251,10 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
     }
     __syncthreads();
     for (int b = tid; b < nbins; b += B) a.acc[b] = 0ull;
-    if (tid == 0) *a.ticket = 0u;
+    if (tid == 0) {
+        *a.ticket = 0u;
+        if (a.claim.nc) *a.claim.ctr = 0u;
+    }
 }
 
 // The voxel of the next rank when the last histogram did not hold it: the
@@ -264,7 +268,7 @@ __global__ void __launch_bounds__(1024) k_select_next(SelectArgs a)
     NextStep ns;
     ns.K = a.st->prefix;
     ns.m = 0xffffffffu;
-    scan_box(a.g, ns);
+    scan_box(a.g, ns, a.claim);
     unsigned int m = ns.m;
     for (int off = 32; off > 0; off >>= 1) {
         const unsigned int o = __shfl_xor(m, off);
@@ -275,6 +279,7 @@ __global__ void __launch_bounds__(1024) k_select_next(SelectArgs a)
     a.st->value_next = key_value(__hip_atomic_load(&a.st->next_key, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT));
     *a.ticket = 0u;
+    if (a.claim.nc) *a.claim.ctr = 0u;
 }
 
 }  // namespace cube
@@ -283,8 +288,8 @@ using namespace cube;
 
 namespace {
 
-// Candidate regions: 2^15 floats per block (64 MiB over 512 blocks).
-constexpr unsigned int CAND_PER_BLOCK = 1u << 15;
+// Candidate regions: 2^24 floats (64 MiB) shared out among the blocks.
+constexpr unsigned int CAND_TOTAL = 1u << 24;
 
 struct SelectWorkspace {
     SelectState *st = nullptr;
@@ -293,7 +298,7 @@ struct SelectWorkspace {
     SelectState *h_st = nullptr;  // pinned
     float *cand = nullptr;
     unsigned int *cand_n = nullptr;
-    int cand_blocks = 0;
+    int cand_blocks = 0;          // blocks the candidate regions were cut for
 };
 
 std::mutex g_smu;
@@ -345,25 +350,31 @@ int select_rank(const Box &b, uint64_t rank, int rank_mode, float *value, uint64
     SelectArgs a;
     memset(&a, 0, sizeof a);
     const int threads = 1024;
-    const int blocks = cu_count() * 2;
-    scan_geom(b, blocks, &a.g);
+    const void *ksel = reinterpret_cast<const void *>(&k_select);
+    // One grid for every pass (pass 2 reads the candidates of its own block
+    // index), sized by the largest pass's LDS: 4096 bins in 8 copies.
+    int blocks = 0, chunks = 0;
+    if ((rc = scan_plan(b, ksel, threads, (size_t)(4096 + 2) * 8 * 4, &blocks, &chunks)))
+        return rc;
+    scan_geom(b, chunks > blocks ? chunks : blocks, &a.g);
     a.st = w->st;
     a.acc = w->acc;
     a.ticket = w->ticket;
+    a.claim.ctr = w->ticket + CHUNK_CTR_WORD;
+    a.claim.nc = chunks;
     if (w->cand_blocks < blocks) {
-        hipFree(w->cand);
         hipFree(w->cand_n);
-        w->cand = nullptr;
         w->cand_n = nullptr;
         w->cand_blocks = 0;
-        if ((e = hipMalloc(&w->cand, (size_t)blocks * CAND_PER_BLOCK * 4)) != hipSuccess ||
-            (e = hipMalloc(&w->cand_n, (size_t)blocks * 4)) != hipSuccess)
+        if ((e = hipMalloc(&w->cand_n, (size_t)blocks * 4)) != hipSuccess)
             return hip_fail(e, "select candidates");
         w->cand_blocks = blocks;
     }
+    if (!w->cand && (e = hipMalloc(&w->cand, (size_t)CAND_TOTAL * 4)) != hipSuccess)
+        return hip_fail(e, "select candidates");
     a.cand = w->cand;
     a.cand_n = w->cand_n;
-    a.cand_cap = CAND_PER_BLOCK;
+    a.cand_cap = CAND_TOTAL / (unsigned int)blocks;
     for (int p = 0; p < 3; ++p) {
         a.pass = p;
         const int nb = 1 << sel_width(p);

@@ -245,3 +245,50 @@ def test_automatic_partition_by_box_size(cs):
     finally:
         cs.cube_set_launch(0, 0, 0, 0)
     del big
+
+
+def _selection_arrays():
+    import synth
+    rng = np.random.default_rng(17)
+    many = np.full(1 << 25, 1.5, np.float32)         # a bucket larger than every region
+    many[::7] = rng.standard_normal(many[::7].size).astype(np.float32)
+    skew = rng.standard_normal(20_000_000).astype(np.float32)
+    skew[:10_000_000] = 0.25                          # one block's region overflows
+    spread = (rng.standard_normal(5_000_003) * 100).astype(np.float32)
+    spread[rng.random(spread.size) < 0.01] = np.nan   # the candidate path
+    wide = (np.exp2(rng.uniform(-60, 60, 300_000)) * rng.choice([-1, 1], 300_000)
+            ).astype(np.float32)
+    wide[rng.random(wide.size) < 0.02] = np.nan      # 64 levels in dozens of top buckets
+    tiny = synth.cube_tensor(synth.WORKLOADS["tiny"], synth.BASE_SEED, device="cuda")
+    return {"many": many, "skew": skew, "spread": spread, "wide": wide,
+            "tiny": tiny.cpu().numpy()}
+
+
+@pytest.mark.parametrize("k", [12, 16])
+def test_selection_median_quantiles(cs, k):
+    """Selection, median and quantiles count exactly, so any partition gives
+    the oracle's values bit for bit (the candidate regions and their
+    overflow fallback included)."""
+    from tests.parity import same_f32
+    levels = [0.0, 0.1, 0.25, 0.5, 0.9, 1.0]
+    levels64 = np.linspace(0, 1, 64)
+    with partition(cs, k):
+        for name, a in _selection_arrays().items():
+            t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            ptr, d = cs.box_of(t)
+            p = cs.cube_describe_plan(ptr, d, cs.CUBE_Q_STATS)
+            assert p["partition"] == "dynamic", p
+            n = int((~np.isnan(a)).sum())
+            for r in (0, n // 3, (n - 1) // 2, n - 1):
+                assert same_f32(cs.select(t, r), oracle.select(a, r)), (name, k, r)
+            m, nv = cs.median(t)
+            assert nv == n and m == oracle.median(a), (name, k)
+            for lv in (levels, levels64):
+                got, nv = cs.quantiles(t, lv)
+                want = oracle.quantiles(a, lv)
+                assert nv == n
+                assert np.array_equal(np.asarray(got).view(np.uint64),
+                                      np.asarray(want).view(np.uint64)), (name, k, len(lv))
+            if name == "wide":
+                assert cs.cube_last_quantile_reads() == 4
+            del t
