@@ -449,6 +449,14 @@ int make_plan(const Box &b, bool stats, int hist_kind_req, int nbins, Plan *p)
         // Dynamic partition: one persistent wave of blocks (the tuned blocks
         // per CU, else all that fit; an explicit grid as given) claiming
         // chunks of about 2^chunk_log2 voxels.
+        // The kernel keeps a ring of wavefront records after its histogram
+        // in LDS: fewer histogram copies if both would not fit one block
+        // (its static LDS is about 1 KB).
+        while (true) {
+            p->lds = pass_lds_bytes(stats, p->hist, nbins, p->copies_log2, threads, true);
+            if (p->lds + 4096 <= 160 * 1024 || p->hist != HIST_LDS || p->copies_log2 == 0) break;
+            --p->copies_log2;
+        }
         const int fit = pass_blocks_per_cu(stats, p->hist, threads, p->lds, p->unroll, true);
         const long long chunks = chunks_of(b.n, chunk_log2);
         if (g_blocks == 0) {

@@ -90,8 +90,16 @@ struct PassArgs {
 hipError_t launch_pass(const PassArgs &a, bool stats, int hist, int threads,
                        int blocks, size_t lds_bytes, int unroll, hipStream_t s);
 
-// Dynamic LDS bytes a pass needs.
-size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int threads);
+// Dynamic LDS bytes a pass needs (`dynamic`: of the dynamic-partition
+// kernel, which keeps a ring of wavefront records after its histogram).
+size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int threads,
+                      bool dynamic = false);
+// Where that ring starts in the dynamic LDS, in 32-bit words (16-byte
+// aligned, after the LDS histogram if there is one).
+__host__ __device__ inline int dyn_ring_offset_words(bool lds_hist, int nbins, int copies_log2)
+{
+    return lds_hist ? (((nbins + 2) << copies_log2) + 3) & ~3 : 0;
+}
 
 // Occupancy of one pass configuration: resident blocks per CU.
 // `dynamic`: of the dynamic-partition kernel.

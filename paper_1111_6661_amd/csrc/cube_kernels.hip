@@ -100,10 +100,14 @@ __global__ void __launch_bounds__(1024) k_pass_dyn(PassArgs a)
     extern __shared__ unsigned int lds[];
     __shared__ unsigned int s_last;
     __shared__ int s_chunk;
-    __shared__ WaveRec s_parts[2][MAX_WAVES];  // wave records of the last two chunks
+    __shared__ int s_ids[MAX_WAVES];  // the chunks whose parts the ring holds
     const int tid = threadIdx.x;
     const int wid = tid >> 6, nw = blockDim.x >> 6;
     constexpr int ACC = CUBE_ACCUM_FP64MERGE;
+    // The ring of wavefront records (dynamic LDS after the histogram): nw
+    // chunks of nw records each.
+    WaveRec *ring = reinterpret_cast<WaveRec *>(
+        lds + dyn_ring_offset_words(HIST == HIST_LDS, a.nbins, a.copies_log2));
 
     Hist H;
     const HistRange r0 = {0.f, 0.f, 0.f, 0};
@@ -122,7 +126,7 @@ __global__ void __launch_bounds__(1024) k_pass_dyn(PassArgs a)
     else __syncthreads();
 
     long long since_flush = 0;  // voxels counted in LDS since it was last zeroed
-    int par = 0;
+    int filled = 0;             // chunks in the ring (uniform)
     while (true) {
         const int c = s_chunk;
         if (c >= nc) break;
@@ -149,19 +153,25 @@ __global__ void __launch_bounds__(1024) k_pass_dyn(PassArgs a)
             scan_units<STATS, HIST, ACC, U>(g, u0, u1, L, W, H);
         else
             scan_units<STATS, HIST_NONE, ACC, U>(g, u0, u1, L, W, H);
-        write_wave_record<STATS, ACC>(L, W, &s_parts[par][wid]);
+        write_wave_record<STATS, ACC>(L, W, &ring[filled * nw + wid]);
+        if (tid == 0) s_ids[filled] = c;
         __syncthreads();  // every part written; every thread has read s_chunk
         if (tid == 0) s_chunk = (int)(early ? next : atomicAdd(ctr, 1u));
         __syncthreads();
-        // The first wavefront merges this chunk's parts while the others
-        // start on the next chunk.  The parts alternate between two buffers:
-        // this one is written again at the end of the chunk after next, past
-        // the first barrier of the next chunk, which the first wavefront
-        // reaches only after this merge.
-        if (wid == 0)
-            write_chunk_record<STATS>(s_parts[par], nw, reinterpret_cast<ChunkRec *>(a.recs) + c);
-        par ^= 1;
+        // When the ring is full, every wavefront merges one of its chunks
+        // (one merge time per nw chunks, not one per chunk on the critical
+        // path), and a barrier frees the ring.
+        if (++filled == nw) {
+            write_chunk_record<STATS>(&ring[wid * nw], nw,
+                                      reinterpret_cast<ChunkRec *>(a.recs) + s_ids[wid]);
+            __syncthreads();
+            filled = 0;
+        }
     }
+    // The chunks left in the ring (published by the loop's last barrier).
+    if (wid < filled)
+        write_chunk_record<STATS>(&ring[wid * nw], nw,
+                                  reinterpret_cast<ChunkRec *>(a.recs) + s_ids[wid]);
     if (HIST == HIST_LDS) hist_flush(lds, a.nbins, a.copies_log2, a.hist_acc);
 
     if (!last_to_arrive(a.ticket, gridDim.x, &s_last)) return;
@@ -187,10 +197,15 @@ __global__ void __launch_bounds__(1024) k_pass_dyn(PassArgs a)
     }
 }
 
-size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int threads)
+size_t pass_lds_bytes(bool stats, int hist, int nbins, int copies_log2, int threads,
+                      bool dynamic)
 {
     (void)stats;
-    (void)threads;
+    if (dynamic) {
+        const size_t nw = (size_t)threads / 64;
+        return (size_t)dyn_ring_offset_words(hist == HIST_LDS, nbins, copies_log2) * 4u +
+               nw * nw * sizeof(WaveRec);
+    }
     if (hist == HIST_LDS || hist == HIST_HOT)
         return (size_t)(nbins + 2) * ((size_t)1 << copies_log2) * 4u;
     return 0;
