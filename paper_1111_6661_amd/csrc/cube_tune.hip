@@ -150,7 +150,10 @@ int cube_autotune(const float *ptr, const int64_t *dims, int32_t kind, float lo,
     };
     const int prev_hot = hot_override();
     const int prev_chunk = chunk_override();
+    // Bring the shader clock up first: after idle it ramps over some tens of
+    // milliseconds of sustained load, which would slow the first candidates.
     rc = CUBE_OK;
+    for (int i = 0; i < 16 && !rc; ++i) rc = run_one();
     for (int part : part_c)
     for (int hot : hot_c)
     for (int t : threads_c)
