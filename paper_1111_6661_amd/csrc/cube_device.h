@@ -19,6 +19,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "cube_internal.h"
 
 namespace cube {
@@ -351,6 +353,123 @@ __device__ Summary<T> merge_records(const R *recs, int n_recs)
     Summary<T> t = ws[0];
     for (int w = 1; w < nw; ++w) summary_merge(t, ws[w]);
     return t;
+}
+
+// A fixed-order sum over the block of one double and the counts and
+// extrema that travel with it: an xor-tree inside each wavefront (the lower
+// lane of each pair on the left), then the wavefront results in order.
+// Every thread gets the result.
+struct BlockSums {
+    double s;
+    unsigned long long nv, below, above;
+    float mn, mx;
+};
+
+__device__ __forceinline__ BlockSums block_sums(BlockSums v)
+{
+    for (int off = 1; off < 64; off <<= 1) {
+        const double os = __shfl_xor(v.s, off);
+        const unsigned long long onv = __shfl_xor(v.nv, off);
+        const unsigned long long ob = __shfl_xor(v.below, off);
+        const unsigned long long oa = __shfl_xor(v.above, off);
+        const float omn = __shfl_xor(v.mn, off), omx = __shfl_xor(v.mx, off);
+        v.s = (threadIdx.x & off) == 0 ? v.s + os : os + v.s;
+        v.nv += onv;
+        v.below += ob;
+        v.above += oa;
+        v.mn = fminf(v.mn, omn);
+        v.mx = fmaxf(v.mx, omx);
+    }
+    __shared__ BlockSums ws[MAX_WAVES];
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();  // a previous call's readers are done with ws
+    if ((threadIdx.x & 63) == 0) ws[wid] = v;
+    __syncthreads();
+    BlockSums t = ws[0];
+    for (int w = 1; w < nw; ++w) {
+        t.s += ws[w].s;
+        t.nv += ws[w].nv;
+        t.below += ws[w].below;
+        t.above += ws[w].above;
+        t.mn = fminf(t.mn, ws[w].mn);
+        t.mx = fmaxf(t.mx, ws[w].mx);
+    }
+    return t;
+}
+
+// The global stage over chunk records in two sweeps, with no division per
+// record: the counts and the sum of n_c * mean_c give the mean, then the sum
+// of m2_c + n_c * (mean_c - mean)^2 gives M2 (the exact combination of the
+// chunk summaries, the identity the pairwise update of Chan, Golub &
+// LeVeque applies two at a time), both in FP64.  Thread t takes records t,
+// t + B, ... (coalesced loads, four in flight), then block_sums fixes the
+// rest of the order.  Deterministic for a given record count and block size.
+__device__ Summary<double> merge_chunk_records(const ChunkRec *recs, int n_recs)
+{
+    const int tid = threadIdx.x, B = blockDim.x;
+    BlockSums a = {0.0, 0ull, 0ull, 0ull, INFINITY, -INFINITY};
+    int r = tid;
+    for (; r + 3 * B < n_recs; r += 4 * B) {
+        ChunkRec c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = recs[r + k * B];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a.below += c[k].below;
+            a.above += c[k].above;
+            if (c[k].n_valid == 0) continue;
+            a.nv += c[k].n_valid;
+            a.mn = fminf(a.mn, c[k].mn);
+            a.mx = fmaxf(a.mx, c[k].mx);
+            a.s += (double)c[k].n_valid * c[k].mean;
+        }
+    }
+    for (; r < n_recs; r += B) {
+        const ChunkRec c = recs[r];
+        a.below += c.below;
+        a.above += c.above;
+        if (c.n_valid == 0) continue;
+        a.nv += c.n_valid;
+        a.mn = fminf(a.mn, c.mn);
+        a.mx = fmaxf(a.mx, c.mx);
+        a.s += (double)c.n_valid * c.mean;
+    }
+    const BlockSums t = block_sums(a);
+    const double mean = t.nv ? t.s / (double)t.nv : 0.0;
+    BlockSums m = {0.0, 0ull, 0ull, 0ull, INFINITY, -INFINITY};
+    for (r = tid; r + 3 * B < n_recs; r += 4 * B) {
+        double mu[4], q[4];
+        unsigned long long nn[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            mu[k] = recs[r + k * B].mean;
+            q[k] = recs[r + k * B].m2;
+            nn[k] = recs[r + k * B].n_valid;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (nn[k] == 0) continue;
+            const double d = mu[k] - mean;
+            m.s += q[k] + (double)nn[k] * d * d;
+        }
+    }
+    for (; r < n_recs; r += B) {
+        const ChunkRec &c = recs[r];
+        if (c.n_valid == 0) continue;
+        const double d = c.mean - mean;
+        m.s += c.m2 + (double)c.n_valid * d * d;
+    }
+    const BlockSums u = block_sums(m);
+    Summary<double> S;
+    S.n = (double)t.nv;
+    S.mean = mean;
+    S.m2 = u.s;
+    S.mn = t.mn;
+    S.mx = t.mx;
+    S.nv = t.nv;
+    S.below = t.below;
+    S.above = t.above;
+    return S;
 }
 
 // One tile: U float4 loads per lane, lane stride B (a wavefront reads 1 KB
@@ -755,7 +874,11 @@ __device__ void finish_stats(const R *recs, int n_recs, int accum_mode,
     float fmn, fmx;
     double mean, m2;
     if (accum_mode == CUBE_ACCUM_FP64MERGE) {
-        const Summary<double> S = merge_records<double, ACC, R>(recs, n_recs);
+        Summary<double> S;
+        if constexpr (std::is_same<R, ChunkRec>::value)
+            S = merge_chunk_records(recs, n_recs);
+        else
+            S = merge_records<double, ACC, R>(recs, n_recs);
         nv = S.nv; below = S.below; above = S.above;
         fmn = S.mn; fmx = S.mx; mean = S.mean; m2 = S.m2;
     } else {

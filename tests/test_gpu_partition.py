@@ -292,3 +292,30 @@ def test_selection_median_quantiles(cs, k):
             if name == "wide":
                 assert cs.cube_last_quantile_reads() == 4
             del t
+
+
+def test_extended_reals_and_offsets_across_chunks(cs):
+    """Infinities and NaN payloads in some chunks only, a large offset, and
+    blank chunks: the chunk records' merge gives the oracle's reading."""
+    rng = np.random.default_rng(5)
+    base = rng.standard_normal(300_017).astype(np.float32)
+    base[::97] = np.nan
+    cases = {}
+    a = base.copy(); a[123_457] = np.inf
+    cases["plus-inf"] = a
+    a = base.copy(); a[200_000] = -np.inf
+    cases["minus-inf"] = a
+    a = base.copy(); a[5] = np.inf; a[290_000] = -np.inf
+    cases["both-inf"] = a
+    cases["offset"] = (1e4 + rng.standard_normal(1_000_003) * 1e-3).astype(np.float32)
+    a = base.copy(); a[:150_000] = np.nan
+    cases["blank-first-half"] = a
+    cases["constant"] = np.full(100_000, 3.25, np.float32)
+    with partition(cs, 12):
+        for name, a in cases.items():
+            t = torch.from_numpy(a).cuda()
+            ref = oracle.stats(a)
+            assert_stats_match(cs.stats(t), ref, name)
+            st, c = cs.stats_hist(t, -1.0, 2.0, 64)
+            assert_stats_match(st, ref, name + " fused")
+            assert_counts_match(c, oracle.hist(a, -1.0, 2.0, 64), name)
