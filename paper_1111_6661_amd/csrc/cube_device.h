@@ -397,68 +397,78 @@ __device__ __forceinline__ BlockSums block_sums(BlockSums v)
     return t;
 }
 
-// The global stage over chunk records in two sweeps, with no division per
-// record: the counts and the sum of n_c * mean_c give the mean, then the sum
-// of m2_c + n_c * (mean_c - mean)^2 gives M2 (the exact combination of the
-// chunk summaries, the identity the pairwise update of Chan, Golub &
-// LeVeque applies two at a time), both in FP64.  Thread t takes records t,
-// t + B, ... (coalesced loads, four in flight), then block_sums fixes the
-// rest of the order.  Deterministic for a given record count and block size.
-__device__ Summary<double> merge_chunk_records(const ChunkRec *recs, int n_recs)
+// The two terms each record adds to the two sweeps of the FP64 global
+// stage below: its sum of x, and its sum of (x - mean)^2 about the global
+// mean.  A chunk record holds (n, mean_c, m2_c): n * mean_c and
+// m2_c + n * (mean_c - mean)^2.  A wavefront record holds the pivoted sums
+// S1 = sum(x - K), S2 = sum((x - K)^2): n * K + S1 and, with d = K - mean,
+// sum((x - K) + d)^2 = S2 + 2 d S1 + n d^2.  Both forms are exact identities;
+// neither divides.
+__device__ __forceinline__ double sweep1_term(const ChunkRec &c)
+{
+    return (double)c.n_valid * c.mean;
+}
+__device__ __forceinline__ double sweep2_term(const ChunkRec &c, double mean)
+{
+    const double d = c.mean - mean;
+    return c.m2 + (double)c.n_valid * d * d;
+}
+__device__ __forceinline__ double sweep1_term(const WaveRec &w)
+{
+    return (double)w.n_valid * (double)w.K + ((double)w.s1h + (double)w.s1l);
+}
+__device__ __forceinline__ double sweep2_term(const WaveRec &w, double mean)
+{
+    const double d = (double)w.K - mean;
+    const double S1 = (double)w.s1h + (double)w.s1l;
+    const double S2 = (double)w.s2h + (double)w.s2l;
+    return S2 + 2.0 * d * S1 + (double)w.n_valid * d * d;
+}
+
+// The FP64 global stage in two sweeps over the records, with no division
+// per record: the counts and the records' sums of x give the mean, then the
+// records' sums of (x - mean)^2 give M2 -- the exact combination that the
+// pairwise update of Chan, Golub & LeVeque applies two at a time.  Thread t
+// takes records t, t + B, ... (coalesced loads, four in flight), then
+// block_sums fixes the rest of the order.  Deterministic for a given record
+// count and block size.
+template <typename R>
+__device__ Summary<double> merge_two_sweep(const R *recs, int n_recs)
 {
     const int tid = threadIdx.x, B = blockDim.x;
     BlockSums a = {0.0, 0ull, 0ull, 0ull, INFINITY, -INFINITY};
-    int r = tid;
-    for (; r + 3 * B < n_recs; r += 4 * B) {
-        ChunkRec c[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = recs[r + k * B];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            a.below += c[k].below;
-            a.above += c[k].above;
-            if (c[k].n_valid == 0) continue;
-            a.nv += c[k].n_valid;
-            a.mn = fminf(a.mn, c[k].mn);
-            a.mx = fmaxf(a.mx, c[k].mx);
-            a.s += (double)c[k].n_valid * c[k].mean;
-        }
-    }
-    for (; r < n_recs; r += B) {
-        const ChunkRec c = recs[r];
+    auto take1 = [&](const R &c) {
         a.below += c.below;
         a.above += c.above;
-        if (c.n_valid == 0) continue;
+        if (c.n_valid == 0) return;
         a.nv += c.n_valid;
         a.mn = fminf(a.mn, c.mn);
         a.mx = fmaxf(a.mx, c.mx);
-        a.s += (double)c.n_valid * c.mean;
+        a.s += sweep1_term(c);
+    };
+    int r = tid;
+    for (; r + 3 * B < n_recs; r += 4 * B) {
+        R c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = recs[r + k * B];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) take1(c[k]);
     }
+    for (; r < n_recs; r += B) take1(recs[r]);
     const BlockSums t = block_sums(a);
     const double mean = t.nv ? t.s / (double)t.nv : 0.0;
     BlockSums m = {0.0, 0ull, 0ull, 0ull, INFINITY, -INFINITY};
+    auto take2 = [&](const R &c) {
+        if (c.n_valid) m.s += sweep2_term(c, mean);
+    };
     for (r = tid; r + 3 * B < n_recs; r += 4 * B) {
-        double mu[4], q[4];
-        unsigned long long nn[4];
+        R c[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            mu[k] = recs[r + k * B].mean;
-            q[k] = recs[r + k * B].m2;
-            nn[k] = recs[r + k * B].n_valid;
-        }
+        for (int k = 0; k < 4; ++k) c[k] = recs[r + k * B];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (nn[k] == 0) continue;
-            const double d = mu[k] - mean;
-            m.s += q[k] + (double)nn[k] * d * d;
-        }
+        for (int k = 0; k < 4; ++k) take2(c[k]);
     }
-    for (; r < n_recs; r += B) {
-        const ChunkRec &c = recs[r];
-        if (c.n_valid == 0) continue;
-        const double d = c.mean - mean;
-        m.s += c.m2 + (double)c.n_valid * d * d;
-    }
+    for (; r < n_recs; r += B) take2(recs[r]);
     const BlockSums u = block_sums(m);
     Summary<double> S;
     S.n = (double)t.nv;
@@ -874,9 +884,11 @@ __device__ void finish_stats(const R *recs, int n_recs, int accum_mode,
     float fmn, fmx;
     double mean, m2;
     if (accum_mode == CUBE_ACCUM_FP64MERGE) {
+        // Pivoted wavefront records (FP64MERGE partials) and chunk records
+        // take the two-sweep merge; the naive partials keep the pairwise one.
         Summary<double> S;
-        if constexpr (std::is_same<R, ChunkRec>::value)
-            S = merge_chunk_records(recs, n_recs);
+        if constexpr (std::is_same<R, ChunkRec>::value || ACC == CUBE_ACCUM_FP64MERGE)
+            S = merge_two_sweep<R>(recs, n_recs);
         else
             S = merge_records<double, ACC, R>(recs, n_recs);
         nv = S.nv; below = S.below; above = S.above;

@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(1024) k_pass_dyn(PassArgs a)
                                     a.want_range ? a.out_range : nullptr, a.nbins, nv, below,
                                     above);
     } else {
-        const Summary<double> S = merge_chunk_records(recs, nc);
+        const Summary<double> S = merge_two_sweep<ChunkRec>(recs, nc);
         nv = S.nv;
         below = S.below;
         above = S.above;
