@@ -6,7 +6,8 @@
 // flushes its LDS histogram with one 64-bit atomic per non-empty bin, and the
 // last block to finish (a ticket counter) merges every record in a fixed
 // order in FP64 (the global stage) and writes the results.  Results are
-// deterministic for a given launch shape.
+// deterministic for a given launch shape.  k_pass_dyn (below) is the same
+// pass with the box handed out in chunks at run time.
 #include "cube_device.h"
 
 namespace cube {
