@@ -19,11 +19,14 @@
 // running blocks that never wait; the wait is bounded anyway.  If it ever
 // expires the tile is skipped, the batch's error flag and the query's own
 // failure flag are raised, and the query completes marked as failed (its
-// histogram is incomplete); the other queries are unaffected.  The range
-// flag a query's first phase raises carries the launch's epoch (a counter
-// the last block of every launch advances), so a flag left up by an earlier
-// launch -- or raised after its query's second phase already gave up --
-// never releases the tiles of a later launch, graph replays included.
+// histogram is incomplete); the other queries are unaffected.  Each word of
+// the range a query's first phase publishes carries the launch's epoch (a
+// counter the last block of every launch advances), so a range left by an
+// earlier launch -- or published after its query's second phase already
+// gave up -- never releases the tiles of a later launch, graph replays
+// included.  Only the first-phase tiles of two-pass queries take their
+// ticket as soon as their writes are complete; every other tile takes it at
+// the block's next tile boundary (nothing in the launch waits for it).
 // Results of a query do not depend on the other queries of the batch (its
 // tiling and merge order are its own), so a query gives the same bits alone
 // and in any mix.
@@ -47,7 +50,6 @@ struct BatchItem {                 // read-only during a launch
     int32_t kind, nbins;
     HistRange range;               // given range (HIST, FUSED)
     int32_t ntiles1, ntiles2;      // tiles of phase 1 / phase 2
-    long long units_per_tile;
     long long rec1, rec2;          // first record of each phase
     long long acc0;                // first histogram accumulator
     cube_stats_t *out;
@@ -56,14 +58,20 @@ struct BatchItem {                 // read-only during a launch
 
 struct BatchState {                // counters zero between launches
     unsigned int done1, done2;
-    unsigned int ready;            // epoch tag of the launch whose range is published
     unsigned int failed;           // a second-phase tile gave up (this launch)
-    HistRange range;
+    unsigned int pad;
+    // The published [min, max] range of a two-pass query: lo, hi, scale and
+    // ok, each in the low half of a 64-bit word whose high half is the epoch
+    // tag of the launch that published it.  A reader takes the range when
+    // all four tags are its own launch's: every word is read and written
+    // whole, so no fence is needed between the flag and the data.
+    unsigned long long rng[4];
 };
 
 struct BatchTile {
     int32_t item, phase;
     int32_t local, pad;            // tile index within the item's phase
+    long long u0, u1;              // its work units [u0, u1)
 };
 
 struct BatchArgs {
@@ -71,6 +79,7 @@ struct BatchArgs {
     BatchState *state;
     const BatchTile *tiles;
     int32_t n_tiles, copies_log2;
+    int32_t lds_words;             // the dynamic LDS histogram area
     WaveRec *recs;
     unsigned long long *acc;
     unsigned int *ctl;             // [0] next tile, [1] exit ticket, [2] error flag
@@ -84,6 +93,13 @@ struct BatchArgs {
 
 constexpr unsigned int DONE_FAILED = 0x80000000u;
 
+__device__ __forceinline__ long long uniform_ll(long long v)
+{
+    const unsigned long long u = (unsigned long long)v;
+    return (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                       (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)u));
+}
+
 template <bool STATS, int HIST, int U>
 __device__ void batch_scan(const BatchItem &it, long long u0, long long u1, Lane &L, Wave &W,
                            const Hist &H)
@@ -91,160 +107,291 @@ __device__ void batch_scan(const BatchItem &it, long long u0, long long u1, Lane
     scan_units<STATS, HIST, CUBE_ACCUM_FP64MERGE, U>(it.g, u0, u1, L, W, H);
 }
 
+// The LDS histogram flush of the batched launch, which keeps its LDS
+// histogram zero between tiles: each thread reads its bins' copies as
+// 16-byte words (C >= 4) and writes zero back to the words it read.  Slot 0,
+// where lanes outside the range add, is never read and never cleared.
+// Starts with a barrier (every LDS add of the tile is done); the cleared
+// words are not added to before the completion's barriers.
+__device__ __forceinline__ void hist_flush_clear(unsigned int *lds, int nbins, int copies_log2,
+                                                 unsigned long long *acc)
+{
+    __syncthreads();
+    const int C = 1 << copies_log2;
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+        const int last = b == nbins - 1 ? 2 : 1;  // floor(u) == nbins belongs to the last bin
+        unsigned int sum = 0;
+        for (int k = 1; k <= last; ++k) {
+            unsigned int *w = lds + ((b + k) << copies_log2);
+            if (C >= 4) {
+                uint4 *w4 = reinterpret_cast<uint4 *>(w);
+                for (int c = 0; c < C / 4; ++c) {
+                    const uint4 v = w4[c];
+                    sum += (v.x + v.y) + (v.z + v.w);
+                    w4[c] = make_uint4(0u, 0u, 0u, 0u);
+                }
+            } else {
+                for (int c = 0; c < C; ++c) {
+                    sum += w[c];
+                    w[c] = 0u;
+                }
+            }
+        }
+        if (sum) atomicAdd(&acc[b], (unsigned long long)sum);
+    }
+}
+
+// The merge of one query's phase, by the block that took its last ticket
+// (after an acquire): the records in tile order (FP64), the histogram
+// accumulators, and either the published range (first phase of a two-pass
+// query) or the query's completion flag.  Ends with a barrier.
+__device__ __forceinline__ void batch_merge(const BatchArgs &a, int item, int phase, bool hist_on,
+                                         unsigned int tag, HistRange *s_out)
+{
+    const int tid = threadIdx.x, nw = blockDim.x >> 6;
+    const BatchItem &it = a.items[item];
+    BatchState *st = &a.state[item];
+    const bool stats = phase == 1 && it.kind != BQ_HIST;
+    const bool hist = phase == 2 || it.kind == BQ_HIST || it.kind == BQ_FUSED;
+    const int ntiles = phase == 1 ? it.ntiles1 : it.ntiles2;
+    const WaveRec *recs = a.recs + (phase == 1 ? it.rec1 : it.rec2);
+    unsigned long long *acc = a.acc + it.acc0;
+    const int n_recs = ntiles * nw;
+    unsigned long long nv, below, above;
+    if (stats) {
+        finish_stats<CUBE_ACCUM_FP64MERGE>(recs, n_recs, a.accum_mode, it.g.n_total, it.out,
+                                           it.kind == BQ_MINMAX ? s_out : nullptr, it.nbins, nv,
+                                           below, above);
+    } else {
+        const Summary<float> S = merge_records<float, CUBE_ACCUM_KAHAN32>(recs, n_recs);
+        nv = S.nv;
+        below = S.below;
+        above = S.above;
+    }
+    if (hist) finish_hist(acc, it.counts, it.nbins, hist_on, below, above, it.g.n_total - nv);
+    __syncthreads();
+    if (tid == 0) {
+        bool finished = true;
+        unsigned int failed = 0u;
+        if (phase == 1) {
+            st->done1 = 0u;
+            if (it.kind == BQ_MINMAX) {
+                // Publish the range, each word tagged with this launch.
+                finished = false;
+                const HistRange r = *s_out;
+                const unsigned long long t = (unsigned long long)tag << 32;
+                __hip_atomic_store(&st->rng[0], t | __float_as_uint(r.lo), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->rng[1], t | __float_as_uint(r.hi), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->rng[2], t | __float_as_uint(r.scale), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->rng[3], t | (unsigned int)r.ok, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {
+            // Every second-phase tile of this query has arrived: its counters
+            // return to zero.  The range words need no reset (the next launch
+            // waits for its own tag).
+            failed = st->failed;
+            st->failed = 0u;
+            st->done2 = 0u;
+        }
+        if (finished && a.done_flags) {
+            // The query's outputs are complete: tell the host (a system-scope
+            // release store orders the outputs first).
+            __hip_atomic_store(&a.done_flags[item], a.gen | (failed ? DONE_FAILED : 0u),
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    // The merge's shared memory is reused by the next tile.
+    __syncthreads();
+}
+
 // U: float4 loads per lane per pipelined tile step (2 or 4, the rule's).
 template <int U>
 __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
 {
-    extern __shared__ unsigned int lds[];
-    __shared__ int s_tile;
-    __shared__ unsigned int s_flag, s_tag;
-    __shared__ HistRange s_range;
+    extern __shared__ __align__(16) unsigned int lds[];
+    __shared__ int s_tile, s_next;
+    __shared__ BatchTile s_desc;
+    __shared__ unsigned int s_flag, s_last, s_tag;
+    __shared__ HistRange s_range, s_pub;
     const int tid = threadIdx.x, wid = tid >> 6, nw = blockDim.x >> 6;
+    const long long ahead_span = 2ll * gridDim.x;
 
-    // This launch's epoch tag (never 0).  The epoch only changes when the
-    // last block leaves, after every block has read it here.
-    if (tid == 0)
+    // Tiles are claimed by thread 0 at the end of the previous tile, in the
+    // same round trip as the tickets, and the claimed tile's descriptor is
+    // staged in LDS there, so a tile starts without waiting on memory.  While
+    // more than two grids' worth of tiles lie beyond the next tile, the block
+    // also holds the tile after it (claimed one tile ahead: its claim then
+    // needs no answer from the claim before it).  Nearer the end of the list
+    // a block holds no tile that an idle block could be working on (a short
+    // batch would otherwise run on half its blocks, two tiles each).  A
+    // first-phase tile held ahead is always held by a block working on an
+    // earlier first-phase tile (every first-phase tile precedes every
+    // second-phase tile in the list), which never waits, so every first-phase
+    // tile is still processed and second-phase waits end.
+    if (tid == 0) {
+        // This launch's epoch tag (never 0).  The epoch only changes when the
+        // last block leaves, after every block has read it here.
         s_tag = (__hip_atomic_load(&a.ctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
                  0x7fffffffu) + 1u;
+        const int t0 = (int)atomicAdd(&a.ctl[0], 1u);
+        s_next = (long long)t0 + ahead_span < (long long)a.n_tiles
+                     ? (int)atomicAdd(&a.ctl[0], 1u) : -1;
+        if (t0 < a.n_tiles) s_desc = a.tiles[t0];
+        s_tile = t0;
+    }
+    // The LDS histogram is zero between tiles (each flush clears what it
+    // read), so it is cleared once here.
+    for (int i = tid; i < a.lds_words; i += blockDim.x) lds[i] = 0u;
     __syncthreads();
     const unsigned int tag = s_tag;
 
-    // While more than two grids' worth of tiles lie beyond the current one,
-    // thread 0 claims the next tile as the current one starts, so the
-    // claim's round trip overlaps the scan; nearer the end of the list it
-    // claims after the tile, so that a block never holds a tile that an idle
-    // block could be working on (a short batch would otherwise run on half
-    // its blocks, two tiles each).  A claimed first-phase tile is always held
-    // by a block working on an earlier first-phase tile (every first-phase
-    // tile precedes every second-phase tile in the list), which never waits,
-    // so every first-phase tile is still processed and second-phase waits end.
-    if (tid == 0) s_tile = (int)atomicAdd(&a.ctl[0], 1u);
-    __syncthreads();
+    // The ticket of a tile whose completion releases nothing inside the
+    // launch (every tile but the first-phase tiles of two-pass queries) is
+    // taken one tile late, at the next tile's end or when the block leaves:
+    // by then its writes are long complete, so no wave waits for them.
+    // Pending: its query and phase (uniform), or item -1.
+    int pend_item = -1, pend_phase = 0;
+    bool pend_hist_on = false;
+
     while (true) {
-        const int t = s_tile;
-        if (t >= a.n_tiles) break;
-        const bool early = (long long)t + 2ll * gridDim.x < (long long)a.n_tiles;
-        unsigned int next = 0u;
-        if (tid == 0 && early) next = atomicAdd(&a.ctl[0], 1u);
-        const BatchTile tile = a.tiles[t];
-        const BatchItem &it = a.items[tile.item];
-        BatchState *st = &a.state[tile.item];
-        const long long u0 = (long long)tile.local * it.units_per_tile;
-        const long long u1 = min(u0 + it.units_per_tile, it.g.n_units);
-        unsigned long long *acc = a.acc + it.acc0;
+        // Uniform values, so the item's fields are read with scalar loads.
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        const bool more = t < a.n_tiles;
+        int item = 0, phase = 1, local = 0;
+        bool gate = false, hist_on = false;
+        if (more) {
+            item = __builtin_amdgcn_readfirstlane(s_desc.item);
+            phase = __builtin_amdgcn_readfirstlane(s_desc.phase);
+            local = __builtin_amdgcn_readfirstlane(s_desc.local);
+            const BatchItem &it = a.items[item];
+            BatchState *st = &a.state[item];
+            const long long u0 = uniform_ll(s_desc.u0), u1 = uniform_ll(s_desc.u1);
+            unsigned long long *acc = a.acc + it.acc0;
 
-        // The histogram range of this tile.
-        HistRange range = it.range;
-        bool skip = false;
-        if (tile.phase == 2) {
-            if (tid == 0) {
-                unsigned int spins = 0;
-                s_flag = 1u;
-                // Relaxed polls, then one acquire fence once the flag is up.
-                // A spin limit of 0 (a test setting) gives up at once.
-                while (a.spin_limit == 0u ||
-                       __hip_atomic_load(&st->ready, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) != tag) {
-                    if (a.spin_limit == 0u || ++spins > a.spin_limit) {
-                        atomicOr(&a.ctl[2], 1u);
-                        atomicOr(&st->failed, 1u);
-                        s_flag = 0u;
-                        break;
+            // The histogram range of this tile.
+            HistRange range = it.range;
+            bool skip = false;
+            if (phase == 2) {
+                if (tid == 0) {
+                    // Relaxed polls of the four tagged words.  A spin limit of
+                    // 0 (a test setting) gives up at once.
+                    unsigned int spins = 0;
+                    unsigned long long w[4];
+                    s_flag = 1u;
+                    while (true) {
+                        bool up = a.spin_limit != 0u;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            w[k] = __hip_atomic_load(&st->rng[k], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                            up = up && (unsigned int)(w[k] >> 32) == tag;
+                        }
+                        if (up) break;
+                        if (a.spin_limit == 0u || ++spins > a.spin_limit) {
+                            atomicOr(&a.ctl[2], 1u);
+                            atomicOr(&st->failed, 1u);
+                            s_flag = 0u;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
                     }
-                    __builtin_amdgcn_s_sleep(8);
-                }
-                if (s_flag) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    s_range = st->range;
-                }
-            }
-            __syncthreads();
-            skip = s_flag == 0u;
-            range = s_range;
-        }
-        const bool stats = tile.phase == 1 && it.kind != BQ_HIST;
-        const bool hist = tile.phase == 2 || it.kind == BQ_HIST || it.kind == BQ_FUSED;
-
-        Hist H;
-        const bool hist_on = hist && range.ok == 1;
-        hist_setup(H, range, it.nbins, a.copies_log2, lds, acc);
-        Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        Wave W = {0.f, 0, 0ull, 0ull, 0ull};
-        if (hist) lds_zero(lds, it.nbins, a.copies_log2);
-        if (!skip) {
-            if (stats && hist_on)
-                batch_scan<true, HIST_LDS, U>(it, u0, u1, L, W, H);
-            else if (stats)
-                batch_scan<true, HIST_NONE, U>(it, u0, u1, L, W, H);
-            else if (hist_on)
-                batch_scan<false, HIST_LDS, U>(it, u0, u1, L, W, H);
-            else  // an invalid [min, max] range bins nothing
-                batch_scan<false, HIST_NONE, U>(it, u0, u1, L, W, H);
-        }
-        const long long rec0 = tile.phase == 1 ? it.rec1 : it.rec2;
-        WaveRec *recs = a.recs + rec0;
-        if (stats)
-            write_wave_record<true, CUBE_ACCUM_FP64MERGE, true>(
-                L, W, &recs[(long long)tile.local * nw + wid]);
-        else
-            write_wave_record<false, CUBE_ACCUM_FP64MERGE, true>(
-                L, W, &recs[(long long)tile.local * nw + wid]);
-        if (hist) hist_flush(lds, it.nbins, a.copies_log2, acc);
-
-        // Completion of the query's phase: the last tile merges.  The records
-        // are written through the L2 and the counts are atomics, so no L2
-        // write-back is needed (see last_to_arrive_wt).
-        const int ntiles = tile.phase == 1 ? it.ntiles1 : it.ntiles2;
-        if (last_to_arrive_wt(tile.phase == 1 ? &st->done1 : &st->done2, (unsigned int)ntiles,
-                              &s_flag)) {
-            const int n_recs = ntiles * nw;
-            unsigned long long nv, below, above;
-            if (stats) {
-                finish_stats<CUBE_ACCUM_FP64MERGE>(recs, n_recs, a.accum_mode, it.g.n_total,
-                                                   it.out, it.kind == BQ_MINMAX ? &st->range
-                                                                                : nullptr,
-                                                   it.nbins, nv, below, above);
-            } else {
-                const Summary<float> S = merge_records<float, CUBE_ACCUM_KAHAN32>(recs, n_recs);
-                nv = S.nv;
-                below = S.below;
-                above = S.above;
-            }
-            if (hist)
-                finish_hist(acc, it.counts, it.nbins, hist_on, below, above,
-                            it.g.n_total - nv);
-            __syncthreads();
-            if (tid == 0) {
-                bool finished = true;
-                unsigned int failed = 0u;
-                if (tile.phase == 1) {
-                    st->done1 = 0u;
-                    if (it.kind == BQ_MINMAX) {
-                        // A release store: it orders the range (and, over
-                        // the barrier, every thread's writes) before the flag.
-                        finished = false;
-                        __hip_atomic_store(&st->ready, tag, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (s_flag) {
+                        HistRange r;
+                        r.lo = __uint_as_float((unsigned int)w[0]);
+                        r.hi = __uint_as_float((unsigned int)w[1]);
+                        r.scale = __uint_as_float((unsigned int)w[2]);
+                        r.ok = (int32_t)(unsigned int)w[3];
+                        s_range = r;
                     }
-                } else {
-                    // Every second-phase tile of this query has arrived: its
-                    // counters return to zero.  The range flag needs no reset
-                    // (the next launch waits for its own tag).
-                    failed = st->failed;
-                    st->failed = 0u;
-                    st->done2 = 0u;
                 }
-                if (finished && a.done_flags) {
-                    // The query's outputs are complete: tell the host (a
-                    // system-scope release store orders the outputs first).
-                    __hip_atomic_store(&a.done_flags[tile.item],
-                                       a.gen | (failed ? DONE_FAILED : 0u), __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_SYSTEM);
-                }
+                __syncthreads();
+                skip = s_flag == 0u;
+                range = s_range;
             }
+            const bool stats = phase == 1 && it.kind != BQ_HIST;
+            const bool hist = phase == 2 || it.kind == BQ_HIST || it.kind == BQ_FUSED;
+            gate = phase == 1 && it.kind == BQ_MINMAX;
+
+            Hist H;
+            hist_on = hist && range.ok == 1;
+            hist_setup(H, range, it.nbins, a.copies_log2, lds, acc);
+            Lane L = {INFINITY, -INFINITY, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            Wave W = {0.f, 0, 0ull, 0ull, 0ull};
+            if (!skip) {
+                if (stats && hist_on)
+                    batch_scan<true, HIST_LDS, U>(it, u0, u1, L, W, H);
+                else if (stats)
+                    batch_scan<true, HIST_NONE, U>(it, u0, u1, L, W, H);
+                else if (hist_on)
+                    batch_scan<false, HIST_LDS, U>(it, u0, u1, L, W, H);
+                else  // an invalid [min, max] range bins nothing
+                    batch_scan<false, HIST_NONE, U>(it, u0, u1, L, W, H);
+            }
+            // The pending tile's writes, issued a tile ago, are complete
+            // before this tile's are issued.
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            WaveRec *recs = a.recs + (phase == 1 ? it.rec1 : it.rec2);
+            if (stats)
+                write_wave_record<true, CUBE_ACCUM_FP64MERGE, true>(
+                    L, W, &recs[(long long)local * nw + wid]);
+            else
+                write_wave_record<false, CUBE_ACCUM_FP64MERGE, true>(
+                    L, W, &recs[(long long)local * nw + wid]);
+            if (hist) hist_flush_clear(lds, it.nbins, a.copies_log2, acc);
+            // A gating tile's own writes complete before its ticket.
+            if (gate) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         }
-        if (tid == 0) s_tile = (int)(early ? next : atomicAdd(&a.ctl[0], 1u));
+        if (!more && pend_item < 0) break;
+
+        // Completion.  The records are written through the L2 and the counts
+        // are atomics: once every wavefront has waited for its own writes,
+        // they are performed at device scope, and a ticket needs no L2
+        // write-back (see last_to_arrive_wt).  Thread 0 sends the tickets,
+        // the claim and the next descriptor's load together.
         __syncthreads();
+        if (tid == 0) {
+            unsigned int last = 0u;
+            if (pend_item >= 0) {
+                const BatchItem &ip = a.items[pend_item];
+                BatchState *sp = &a.state[pend_item];
+                const unsigned int tk = atomicAdd(pend_phase == 1 ? &sp->done1 : &sp->done2, 1u);
+                if (tk == (unsigned int)(pend_phase == 1 ? ip.ntiles1 : ip.ntiles2) - 1u)
+                    last |= 1u;
+            }
+            if (more) {
+                if (gate) {
+                    const BatchItem &it = a.items[item];
+                    const unsigned int tk = atomicAdd(&a.state[item].done1, 1u);
+                    if (tk == (unsigned int)it.ntiles1 - 1u) last |= 2u;
+                }
+                int nxt = s_next, ahead = -1;
+                if (nxt >= 0) {
+                    if ((long long)nxt + ahead_span < (long long)a.n_tiles)
+                        ahead = (int)atomicAdd(&a.ctl[0], 1u);
+                } else {
+                    nxt = (int)atomicAdd(&a.ctl[0], 1u);
+                }
+                if (nxt < a.n_tiles) s_desc = a.tiles[nxt];
+                s_tile = nxt;
+                s_next = ahead;
+            }
+            if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_last = last;
+        }
+        __syncthreads();
+        const unsigned int last = s_last;
+        if (last & 1u) batch_merge(a, pend_item, pend_phase, pend_hist_on, tag, &s_pub);
+        if (last & 2u) batch_merge(a, item, phase, hist_on, tag, &s_pub);
+        if (!more) break;
+        pend_item = gate ? -1 : item;
+        pend_phase = phase;
+        pend_hist_on = hist_on;
     }
 
     // The last block to leave returns the work counters to zero and starts
@@ -518,6 +665,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     // Validate every query and plan its tiles.
     std::vector<BatchItem> items((size_t)n);
     std::vector<long long> order((size_t)n);
+    std::vector<long long> upts((size_t)n);  // work units per tile
     size_t n_tiles = 0, n_recs = 0, n_acc = 0;
     int max_bins = 1;
     // The automatic rule: the autotuner's candidate, else the tuned one,
@@ -578,8 +726,9 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
         g.n_units = box.n == 0 ? 0 : g.ny * g.nz * g.segs;
         long long upt = tv / seg;
         if (upt < 1) upt = 1;
-        it.units_per_tile = upt;
+        upts[(size_t)i] = upt;
         const long long nt = g.n_units == 0 ? 1 : (g.n_units + upt - 1) / upt;
+        if (nt > 0x7fffffffLL) return fail(CUBE_EINVAL, "query %d: too many tiles", i);
         it.ntiles1 = (int32_t)nt;
         it.ntiles2 = qq.kind == CUBE_Q_MINMAX ? (int32_t)nt : 0;
         it.rec1 = (long long)n_recs;
@@ -591,10 +740,18 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
         n_tiles += (size_t)(it.ntiles1 + it.ntiles2);
         order[(size_t)i] = i;
     }
-    if (n_tiles > (size_t)0x7fffffff) return fail(CUBE_EINVAL, "too many tiles");
-    int rc = ensure(b, (size_t)n, n_tiles, n_recs, n_acc);
-    if (rc) return rc;
-    drop_graph(b);
+    // Launch shape: one histogram copy layout for the batch, a grid of
+    // resident blocks.
+    hipError_t e;
+    int clog = 0;
+    const size_t lds_budget = (size_t)rule.lds_kib * 1024;
+    while (clog < 5 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= lds_budget) ++clog;
+    b->lds = ((size_t)(max_bins + 2) << clog) * 4;
+    int bpc = 1;
+    if ((e = batch_occupancy(b->threads, b->unroll, b->lds, &bpc)) != hipSuccess)
+        return hip_fail(e, "batch occupancy");
+    if (bpc < 1) bpc = 1;
+    const long long grid = (long long)cu_count() * bpc;
     // Work list: phase-1 tiles, largest queries first, then phase-2 tiles in
     // the same order.
     std::vector<long long> sz((size_t)n);
@@ -605,6 +762,10 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     else
         std::stable_sort(order.begin(), order.end(),
                          [&](long long x, long long y) { return sz[(size_t)x] < sz[(size_t)y]; });
+    if (n_tiles > (size_t)0x7fffffff) return fail(CUBE_EINVAL, "too many tiles");
+    int rc = ensure(b, (size_t)n, n_tiles, n_recs, n_acc);
+    if (rc) return rc;
+    drop_graph(b);
     if ((rc = ensure_done(b, (size_t)n))) return rc;
     // A launch still running on another stream reads the device work list:
     // wait for it.  On the same stream, stream order protects the device
@@ -616,6 +777,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     for (int phase = 1; phase <= 2; ++phase)
         for (long long i : order) {
             const BatchItem &it = items[(size_t)i];
+            const long long upt = upts[(size_t)i];
             const int nt = phase == 1 ? it.ntiles1 : it.ntiles2;
             for (int t = 0; t < nt; ++t) {
                 BatchTile &bt = b->h_tiles[k++];
@@ -623,10 +785,11 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
                 bt.phase = phase;
                 bt.local = t;
                 bt.pad = 0;
+                bt.u0 = (long long)t * upt;
+                bt.u1 = std::min<long long>(bt.u0 + upt, it.g.n_units);
             }
         }
     memcpy(b->h_items, items.data(), (size_t)n * sizeof(BatchItem));
-    hipError_t e;
     if (n > 0 &&
         ((e = hipMemcpyAsync(b->d_items, b->h_items, (size_t)n * sizeof(BatchItem),
                              hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -638,17 +801,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
             return hip_fail(e, "event");
         if ((e = hipEventRecord(b->staged, s)) != hipSuccess) return hip_fail(e, "event record");
     }
-    // Launch shape: one histogram copy layout for the batch, a grid of
-    // resident blocks.
-    int clog = 0;
-    const size_t lds_budget = (size_t)rule.lds_kib * 1024;
-    while (clog < 5 && ((size_t)(max_bins + 2) << (clog + 1)) * 4 <= lds_budget) ++clog;
-    b->lds = ((size_t)(max_bins + 2) << clog) * 4;
-    int bpc = 1;
-    if ((e = batch_occupancy(b->threads, b->unroll, b->lds, &bpc)) != hipSuccess)
-        return hip_fail(e, "batch occupancy");
-    if (bpc < 1) bpc = 1;
-    long long blocks = (long long)cu_count() * bpc;
+    long long blocks = grid;
     if (blocks > (long long)n_tiles) blocks = (long long)n_tiles;
     if (blocks < 1) blocks = 1;
     b->blocks = (int)blocks;
@@ -658,6 +811,7 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
     a.tiles = b->d_tiles;
     a.n_tiles = (int32_t)n_tiles;
     a.copies_log2 = clog;
+    a.lds_words = (int32_t)(b->lds / 4);
     a.recs = b->d_recs;
     a.acc = b->d_acc;
     a.ctl = b->d_ctl;
