@@ -423,8 +423,10 @@ CUBE_API int cube_batch_create(cube_batch_t **out);
 CUBE_API void cube_batch_destroy(cube_batch_t *b);
 /* Tile size in voxels (4096..2^30; default 2^20; 0 = automatic per query)
  * and threads per block (0 = automatic) for later enqueues.  The automatic
- * size is the smallest power of two from 2^18 to 2^20 that cuts the query
- * into at most 512 tiles, so it depends on the query alone.  A query's
+ * size comes from the query's voxel count by the batched launch's rule (the
+ * tuned one, else the default: the smallest power of two from 2^17 to 2^20
+ * that cuts the query into at most 1024 tiles), so it depends on the query
+ * alone.  A query's
  * results depend only on its own data and its tile size, not on the other
  * queries of the batch. */
 CUBE_API int cube_batch_set_tile(cube_batch_t *b, int64_t tile_voxels, int32_t threads);

@@ -709,9 +709,9 @@ int cube_batch_enqueue(cube_batch_t *b, const cube_query_t *q, int32_t n, void *
         it.counts = (unsigned long long *)qq.counts;
         collapse(box, &it.g);
         // The query's tile size: the batch's, or (0) one from the query's own
-        // size by the rule (by default at most 512 tiles of 2^18 to 2^20
-        // voxels: below 2^18 the per-tile completion, a release fence and a
-        // ticket, costs more than the parallelism it buys).  Either way a
+        // size by the rule (by default at most 1024 tiles of 2^17 to 2^20
+        // voxels: smaller tiles pay the per-tile completion, the record
+        // stores and a ticket, more often than the parallelism repays).  Either way a
         // query's tiling depends only on itself, so its results are the same
         // alone and in any mix.
         long long tv = b->tile_voxels;

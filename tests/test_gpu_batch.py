@@ -113,15 +113,15 @@ def test_alone_equals_in_mix(cs):
 
 
 def test_automatic_tile_sizes(cs):
-    """Tile 0: each query takes the smallest power of two from 2^18 to 2^20
-    voxels that cuts it into at most 512 tiles.  Items here take 2^18, 2^19
-    and 2^20; each gives the same bits alone and in the mix, and agrees with
-    the oracle."""
+    """Tile 0: with the default rule each query takes the smallest power of
+    two from 2^17 to 2^20 voxels that cuts it into at most 1024 tiles.  Items
+    here take 2^17, 2^18 and 2^19; each gives the same bits alone and in the
+    mix, and agrees with the oracle."""
     import synth
-    shapes = [(37, 11, 5), (200, 300, 9),            # one tile of 2^18
-              (1000, 1000, 100),                     # 10^8 voxels: 2^18
-              (2048, 1024, 96),                      # 2^27.6 voxels: 2^19
-              (2048, 1024, 160)]                     # 2^28.3 voxels: 2^20 (clamped)
+    shapes = [(37, 11, 5), (200, 300, 9),            # one and five tiles of 2^17
+              (1000, 1000, 100),                     # 10^8 voxels: 2^17
+              (2048, 1024, 96),                      # 2^27.6 voxels: 2^18
+              (2048, 1024, 160)]                     # 2^28.3 voxels: 2^19
     items = [synth.cube_tensor(synth.WORKLOADS["tiny"].scaled(nx, ny, nz), 4200 + k, device="cuda")
              for k, (nx, ny, nz) in enumerate(shapes)]
     kinds = [cs.CUBE_Q_FUSED, cs.CUBE_Q_MINMAX]
