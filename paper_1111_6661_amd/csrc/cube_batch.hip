@@ -24,9 +24,10 @@
 // counter the last block of every launch advances), so a range left by an
 // earlier launch -- or published after its query's second phase already
 // gave up -- never releases the tiles of a later launch, graph replays
-// included.  Only the first-phase tiles of two-pass queries take their
-// ticket as soon as their writes are complete; every other tile takes it at
-// the block's next tile boundary (nothing in the launch waits for it).
+// included.  The first-phase tiles of two-pass queries, and every tile near
+// the end of the list, take their ticket as soon as their writes are
+// complete; every other tile takes it at the block's next tile boundary
+// (nothing in the launch waits for it).
 // Results of a query do not depend on the other queries of the batch (its
 // tiling and merge order are its own), so a query gives the same bits alone
 // and in any mix.
@@ -251,8 +252,10 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
 
     // The ticket of a tile whose completion releases nothing inside the
     // launch (every tile but the first-phase tiles of two-pass queries) is
-    // taken one tile late, at the next tile's end or when the block leaves:
-    // by then its writes are long complete, so no wave waits for them.
+    // taken one tile late, at the next tile's end, while the block holds a
+    // tile ahead (so it has a next tile): by then its writes are long
+    // complete, so no wave waits for them.  Nearer the end of the list every
+    // tile takes its ticket at once, so no merge waits for the block's exit.
     // Pending: its query and phase (uniform), or item -1.
     int pend_item = -1, pend_phase = 0;
     bool pend_hist_on = false;
@@ -261,8 +264,9 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         // Uniform values, so the item's fields are read with scalar loads.
         const int t = __builtin_amdgcn_readfirstlane(s_tile);
         const bool more = t < a.n_tiles;
+        const bool held = __builtin_amdgcn_readfirstlane(s_next) >= 0;
         int item = 0, phase = 1, local = 0;
-        bool gate = false, hist_on = false;
+        bool sync = false, hist_on = false;
         if (more) {
             item = __builtin_amdgcn_readfirstlane(s_desc.item);
             phase = __builtin_amdgcn_readfirstlane(s_desc.phase);
@@ -314,7 +318,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
             }
             const bool stats = phase == 1 && it.kind != BQ_HIST;
             const bool hist = phase == 2 || it.kind == BQ_HIST || it.kind == BQ_FUSED;
-            gate = phase == 1 && it.kind == BQ_MINMAX;
+            sync = (phase == 1 && it.kind == BQ_MINMAX) || !held;
 
             Hist H;
             hist_on = hist && range.ok == 1;
@@ -342,8 +346,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                 write_wave_record<false, CUBE_ACCUM_FP64MERGE, true>(
                     L, W, &recs[(long long)local * nw + wid]);
             if (hist) hist_flush_clear(lds, it.nbins, a.copies_log2, acc);
-            // A gating tile's own writes complete before its ticket.
-            if (gate) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            // A tile that takes its ticket now waits for its own writes.
+            if (sync) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         } else {
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         }
@@ -365,10 +369,12 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
                     last |= 1u;
             }
             if (more) {
-                if (gate) {
+                if (sync) {
                     const BatchItem &it = a.items[item];
-                    const unsigned int tk = atomicAdd(&a.state[item].done1, 1u);
-                    if (tk == (unsigned int)it.ntiles1 - 1u) last |= 2u;
+                    BatchState *st = &a.state[item];
+                    const unsigned int tk = atomicAdd(phase == 1 ? &st->done1 : &st->done2, 1u);
+                    if (tk == (unsigned int)(phase == 1 ? it.ntiles1 : it.ntiles2) - 1u)
+                        last |= 2u;
                 }
                 int nxt = s_next, ahead = -1;
                 if (nxt >= 0) {
@@ -389,7 +395,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         if (last & 1u) batch_merge(a, pend_item, pend_phase, pend_hist_on, tag, &s_pub);
         if (last & 2u) batch_merge(a, item, phase, hist_on, tag, &s_pub);
         if (!more) break;
-        pend_item = gate ? -1 : item;
+        pend_item = sync ? -1 : item;
         pend_phase = phase;
         pend_hist_on = hist_on;
     }
