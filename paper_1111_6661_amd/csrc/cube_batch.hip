@@ -238,9 +238,12 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
         // last block leaves, after every block has read it here.
         s_tag = (__hip_atomic_load(&a.ctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
                  0x7fffffffu) + 1u;
-        const int t0 = (int)atomicAdd(&a.ctl[0], 1u);
-        s_next = (long long)t0 + ahead_span < (long long)a.n_tiles
-                     ? (int)atomicAdd(&a.ctl[0], 1u) : -1;
+        // With more than four grids' worth of tiles, every first claim
+        // (below two grids) leaves more than two grids beyond the tile after
+        // it: one claim of two consecutive tiles takes both.
+        const bool two = (long long)a.n_tiles > 2ll * ahead_span;
+        const int t0 = (int)atomicAdd(&a.ctl[0], two ? 2u : 1u);
+        s_next = two ? t0 + 1 : -1;
         if (t0 < a.n_tiles) s_desc = a.tiles[t0];
         s_tile = t0;
     }
