@@ -74,22 +74,41 @@ struct QuantStep {
     template <int NV>
     __device__ __forceinline__ void operator()(const float (&x)[NV])
     {
+        if (NL == 0) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const float v = x[j];
-            const bool ok = v == v;
-            if (NL == 0) valid += (unsigned int)__popcll(__builtin_amdgcn_ballot_w64(ok));
-            const unsigned int k = order_key(v);
-            if (NL == 0) {
+            for (int j = 0; j < NV; ++j) {
+                const float v = x[j];
+                const bool ok = v == v;
+                valid += (unsigned int)__popcll(__builtin_amdgcn_ballot_w64(ok));
                 // one histogram, blanks skipped (they are rare)
-                if (ok) atomicAdd(&lds[((k >> 20) << clog) + cbase], 1u);
-            } else {
-                // histogram row g: 0 (no wanted prefix) counts nothing
-                unsigned int g = t1[k >> 20];
-                if (NL >= 2) g = t2[(g << w2) | ((k >> (20 - w2)) & ((1u << w2) - 1u))];
-                if (NL >= 3) g = t3[(g << w3) | ((k >> (20 - w2 - w3)) & ((1u << w3) - 1u))];
-                const unsigned int idx = (g << wb) | ((k >> shift) & bmask);
-                if (ok && g != 0u) atomicAdd(&lds[(idx << clog) + cbase], 1u);
+                if (ok) atomicAdd(&lds[((order_key(v) >> 20) << clog) + cbase], 1u);
+            }
+        } else {
+            // Histogram row g of each voxel: 0 (no wanted prefix) counts
+            // nothing.  The tables are read level by level for all NV voxels
+            // before any count is added: the counts live in the same LDS, so
+            // a table read after an add could not be moved ahead of it, and
+            // the voxels' lookups would run one after another.
+            unsigned int k[NV], g[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                k[j] = order_key(x[j]);
+                g[j] = t1[k[j] >> 20];
+            }
+            if (NL >= 2) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j)
+                    g[j] = t2[(g[j] << w2) | ((k[j] >> (20 - w2)) & ((1u << w2) - 1u))];
+            }
+            if (NL >= 3) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j)
+                    g[j] = t3[(g[j] << w3) | ((k[j] >> (20 - w2 - w3)) & ((1u << w3) - 1u))];
+            }
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const unsigned int idx = (g[j] << wb) | ((k[j] >> shift) & bmask);
+                if (x[j] == x[j] && g[j] != 0u) atomicAdd(&lds[(idx << clog) + cbase], 1u);
             }
         }
     }
