@@ -92,6 +92,33 @@ def test_mixed_batch_matches_oracle(cs, tile):
     b.close()
 
 
+def test_replays_take_their_own_range(cs):
+    """Two-pass queries whose cubes change between launches: every relaunch
+    and graph replay bins over the new [min, max], never over a range
+    published by an earlier launch (the range words carry the launch's
+    epoch).  Small tiles give each query many second-phase tiles."""
+    items = make_items(seed=9, n=6)
+    nb = 64
+    outs = Outputs(len(items), nb)
+    qs = queries_for(cs, items, outs, [cs.CUBE_Q_MINMAX], [nb])
+    b = cs.Batch(tile_voxels=4096)
+    b.enqueue(qs)
+    b.check()
+    for i, t in enumerate(items):
+        check_query(cs, outs, i, t, cs.CUBE_Q_MINMAX, nb)
+    for k, launch in enumerate((b.graph_launch, b.relaunch, b.graph_launch, b.graph_launch)):
+        for t in items:
+            t.mul_(1.5).add_(3.0 * (k + 1))   # moves and widens every range
+        outs.out.zero_()
+        outs.cnt.zero_()
+        torch.cuda.synchronize()
+        launch()
+        b.check()
+        for i, t in enumerate(items):
+            check_query(cs, outs, i, t, cs.CUBE_Q_MINMAX, nb)
+    b.close()
+
+
 def test_alone_equals_in_mix(cs):
     items = make_items(seed=9, n=10)
     kinds = [cs.CUBE_Q_MINMAX, cs.CUBE_Q_FUSED, cs.CUBE_Q_STATS]
