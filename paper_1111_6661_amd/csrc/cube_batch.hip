@@ -264,7 +264,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchArgs a)
     bool pend_hist_on = false;
 
     while (true) {
-        // Uniform values, so the item's fields are read with scalar loads.
+        // Uniform values (scalar registers): one address per wavefront for
+        // the item's fields and the tile's bounds.
         const int t = __builtin_amdgcn_readfirstlane(s_tile);
         const bool more = t < a.n_tiles;
         const bool held = __builtin_amdgcn_readfirstlane(s_next) >= 0;
