@@ -88,7 +88,10 @@ struct QuantStep {
             // nothing.  The tables are read level by level for all NV voxels
             // before any count is added: the counts live in the same LDS, so
             // a table read after an add could not be moved ahead of it, and
-            // the voxels' lookups would run one after another.
+            // the voxels' lookups would run one after another.  With two or
+            // three table levels the key fields are single bit-field extracts
+            // (the one-level pass measured slower with them: 2.52 against
+            // 2.34 ms on the brick).
             unsigned int k[NV], g[NV];
 #pragma unroll
             for (int j = 0; j < NV; ++j) {
@@ -98,16 +101,18 @@ struct QuantStep {
             if (NL >= 2) {
 #pragma unroll
                 for (int j = 0; j < NV; ++j)
-                    g[j] = t2[(g[j] << w2) | ((k[j] >> (20 - w2)) & ((1u << w2) - 1u))];
+                    g[j] = t2[(g[j] << w2) | __builtin_amdgcn_ubfe(k[j], 20 - w2, w2)];
             }
             if (NL >= 3) {
 #pragma unroll
                 for (int j = 0; j < NV; ++j)
-                    g[j] = t3[(g[j] << w3) | ((k[j] >> (20 - w2 - w3)) & ((1u << w3) - 1u))];
+                    g[j] = t3[(g[j] << w3) | __builtin_amdgcn_ubfe(k[j], 20 - w2 - w3, w3)];
             }
 #pragma unroll
             for (int j = 0; j < NV; ++j) {
-                const unsigned int idx = (g[j] << wb) | ((k[j] >> shift) & bmask);
+                const unsigned int idx =
+                    (g[j] << wb) | (NL >= 2 ? __builtin_amdgcn_ubfe(k[j], shift, wb)
+                                            : (k[j] >> shift) & bmask);
                 if (x[j] == x[j] && g[j] != 0u) atomicAdd(&lds[(idx << clog) + cbase], 1u);
             }
         }
