@@ -136,6 +136,8 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
 {
     extern __shared__ unsigned int lds[];
     __shared__ unsigned int s_last, s_cnt;
+    __shared__ int s_t;
+    __shared__ unsigned long long s_rank;
     __shared__ unsigned long long s_part[1024];
     const int tid = threadIdx.x, B = blockDim.x;
     const int p = a.pass;
@@ -204,19 +206,36 @@ __global__ void __launch_bounds__(1024) k_select(SelectArgs a)
         if (b < nbins) mine += a.acc[b];
     }
     s_part[tid] = mine;
-    __syncthreads();
+    SelectState st;
     if (tid == 0) {
-        SelectState st = *a.st;
+        st = *a.st;
         if (p == 0 && st.rank_mode == 1 && st.n_valid) {
             st.rank = (st.n_valid - 1) / 2;
             st.want_next = (st.n_valid % 2 == 0) ? 1u : 0u;
         }
         if (p == 0 && st.rank >= st.n_valid) st.error = 1u;
         if (p == 0 && st.want_next && st.rank + 1 >= st.n_valid) st.want_next = 0u;
+        s_rank = st.rank;
+        s_t = B - 1;
+    }
+    // Inclusive prefix sums of the threads' partial counts, then the first
+    // thread whose sum passes the rank (the last one if none does).
+    for (int off = 1; off < B; off <<= 1) {
+        __syncthreads();
+        const unsigned long long v = tid >= off ? s_part[tid - off] : 0ull;
+        __syncthreads();
+        s_part[tid] += v;
+    }
+    __syncthreads();
+    {
+        const unsigned long long r = s_rank;
+        if (tid < B - 1 && s_part[tid] > r && (tid == 0 || s_part[tid - 1] <= r)) s_t = tid;
+    }
+    __syncthreads();
+    if (tid == 0) {
         if (!st.error) {
-            unsigned long long before = 0;
-            int t = 0;
-            while (t < B - 1 && before + s_part[t] <= st.rank) before += s_part[t++];
+            const int t = s_t;
+            unsigned long long before = t > 0 ? s_part[t - 1] : 0ull;
             int b = t * per;
             while (b < nbins - 1 && before + a.acc[b] <= st.rank) before += a.acc[b++];
             const unsigned int up = st.prefix << width;
